@@ -1,0 +1,157 @@
+"""FP64 CPU oracle for recursive solid-angle labeling -- TEST INFRASTRUCTURE.
+
+Plain, slow, obviously correct.  Only `tests/`, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the GPU library neither
+imports nor links it, and the two share no code.
+
+* `liboracle.so` (built from sal_oracle.c with gcc) holds the FP64 pair loop:
+  Van Oosterom-Strackee solid angles with an exact-sign guard, compensated
+  sums, the label rule and an independent radial inside test.
+* `oracle.kuhn` holds the lattice, refinement and boundary rules, written as
+  point location in exact dyadic coordinates.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sal_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile liboracle.so with gcc (-O2, no FP contraction, no fast-math)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-Wall",
+                           "-shared", "-fPIC", "-o", tmp, _SRC, "-lpthread", "-lm"])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        L.oracle_orient3d_sign.argtypes = [f32p] * 4
+        L.oracle_orient3d_sign.restype = ctypes.c_int
+        L.oracle_orient2d_sign.argtypes = [f32p] * 3 + [ctypes.c_int]
+        L.oracle_orient2d_sign.restype = ctypes.c_int
+        L.oracle_tri_solid_angle.argtypes = [f32p] * 4 + [ctypes.POINTER(ctypes.c_int)]
+        L.oracle_tri_solid_angle.restype = ctypes.c_double
+        L.oracle_winding.argtypes = [ctypes.c_int64, f32p, f32p, f32p, ctypes.c_int64, f32p,
+                                     ctypes.c_int64, i32p, ctypes.c_int, f64p, u8p]
+        L.oracle_winding.restype = None
+        L.oracle_label.argtypes = [ctypes.c_int64, f32p, f32p, f32p, ctypes.c_int, i64p, i64p,
+                                   f32p, i32p, i32p, ctypes.c_double, ctypes.c_int, i32p,
+                                   ctypes.c_void_p]
+        L.oracle_label.restype = ctypes.c_int64
+        L.oracle_radial_inside.argtypes = [ctypes.c_int64, f32p, f32p, f32p, f32p, f32p,
+                                           ctypes.c_int64, i32p, ctypes.c_int, u8p]
+        L.oracle_radial_inside.restype = None
+        _lib = L
+    return _lib
+
+
+def host_threads():
+    """Host cores this process may run on."""
+    return len(os.sched_getaffinity(0))
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def orient3d_sign(p, v0, v1, v2):
+    """Exact sign of det[v0 - p, v1 - p, v2 - p] for float32 inputs."""
+    return lib().oracle_orient3d_sign(_f32(p), _f32(v0), _f32(v1), _f32(v2))
+
+
+def orient2d_sign(a, b, c, drop):
+    return lib().oracle_orient2d_sign(_f32(a), _f32(b), _f32(c), int(drop))
+
+
+def tri_solid_angle(p, v0, v1, v2):
+    """(Omega, on_triangle) for one triangle seen from p (float32 inputs)."""
+    on = ctypes.c_int(0)
+    om = lib().oracle_tri_solid_angle(_f32(p), _f32(v0), _f32(v1), _f32(v2), ctypes.byref(on))
+    return om, bool(on.value)
+
+
+def _soa(points):
+    pts = np.asarray(points)
+    assert pts.ndim == 2 and pts.shape[0] == 3
+    return _f32(pts[0]), _f32(pts[1]), _f32(pts[2])
+
+
+def winding(points, v, f, n_threads=0):
+    """Winding numbers w = Omega / 4 pi of one surface at points [3, N]."""
+    x, y, z = _soa(points)
+    n = x.size
+    w = np.empty(n, dtype=np.float64)
+    on = np.empty(n, dtype=np.uint8)
+    vv = _f32(v).reshape(-1)
+    ff = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+    lib().oracle_winding(n, x, y, z, vv.size // 3, vv, ff.size // 3, ff, int(n_threads), w, on)
+    return w, on.astype(bool)
+
+
+def pack_surfaces(surfaces):
+    """Concatenate surfaces (objects with .v, .f, .label) for the C calls."""
+    vert_off = np.zeros(len(surfaces) + 1, dtype=np.int64)
+    tri_off = np.zeros(len(surfaces) + 1, dtype=np.int64)
+    for i, s in enumerate(surfaces):
+        vert_off[i + 1] = vert_off[i] + s.v.shape[0]
+        tri_off[i + 1] = tri_off[i] + s.f.shape[0]
+    verts = _f32(np.concatenate([s.v for s in surfaces]).reshape(-1))
+    tris = np.ascontiguousarray(np.concatenate([s.f for s in surfaces]), dtype=np.int32).reshape(-1)
+    labels = np.array([s.label for s in surfaces], dtype=np.int32)
+    return vert_off, tri_off, verts, tris, labels
+
+
+def label(points, surfaces, threshold=0.5, n_threads=0, want_w=False):
+    """Compartment labels (int32 [N]) of points [3, N]; surfaces outermost
+    first, the later one winning.  Optionally the winding numbers [K, N]."""
+    x, y, z = _soa(points)
+    n = x.size
+    vert_off, tri_off, verts, tris, labs = pack_surfaces(surfaces)
+    out = np.empty(n, dtype=np.int32)
+    w = np.empty((len(surfaces), n), dtype=np.float64) if want_w else None
+    lib().oracle_label(n, x, y, z, len(surfaces), vert_off, tri_off, verts, tris, labs,
+                       float(threshold), int(n_threads), out,
+                       w.ctypes.data if want_w else None)
+    return (out, w) if want_w else out
+
+
+def radial_inside(points, surface, n_threads=0):
+    """Exact star-shaped inside test: 1 inside, 0 outside, 2 on the surface."""
+    x, y, z = _soa(points)
+    n = x.size
+    out = np.empty(n, dtype=np.uint8)
+    c = _f32(np.asarray(surface.center, dtype=np.float64))
+    vv = _f32(surface.v).reshape(-1)
+    ff = np.ascontiguousarray(surface.f, dtype=np.int32).reshape(-1)
+    lib().oracle_radial_inside(n, x, y, z, c, vv, ff.size // 3, ff, int(n_threads), out)
+    return out
+
+
+def radial_label(points, surfaces, n_threads=0):
+    """Labels from the radial test alone (every surface star-shaped about its
+    centre): the later enclosing (or touching) surface wins."""
+    pts = np.asarray(points)
+    out = np.zeros(pts.shape[1], dtype=np.int32)
+    for s in surfaces:
+        r = radial_inside(pts, s, n_threads)
+        out[r > 0] = s.label
+    return out

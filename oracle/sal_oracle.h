@@ -1,0 +1,75 @@
+/*
+ * FP64 CPU oracle for solid-angle labeling.  TEST INFRASTRUCTURE ONLY: it is
+ * called by the tests, by the smoke check and by the CPU-baseline timing of
+ * the benchmark, never by the library it checks.  It shares no code with it.
+ *
+ * What it computes (paper section 2.1.3, Eq. 1, with the |r - r_i|^-3 kernel
+ * that the printed equation omits): for a point p and a closed, outward
+ * oriented triangulated surface S, the winding number
+ *     w(p) = Omega_S(p) / (4 pi),
+ * where Omega_S is the solid angle of S seen from p, summed exactly per flat
+ * triangle with the Van Oosterom-Strackee formula.  A point is enclosed by S
+ * when w >= T, or when it lies on S.  The compartment label is that of the
+ * highest-priority enclosing surface (section 2.1: later in the list = higher
+ * priority), else 0 (the bounding box).
+ *
+ * All inputs are float32 and promoted exactly to double.
+ */
+#ifndef SAL_ORACLE_H
+#define SAL_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Exact sign (-1, 0, +1) of det[v0 - p, v1 - p, v2 - p]. */
+int oracle_orient3d_sign(const float p[3], const float v0[3], const float v1[3],
+                         const float v2[3]);
+
+/* Exact sign of (b - a) x (c - a) projected on the plane that drops axis
+ * `drop` (0 = x, 1 = y, 2 = z). */
+int oracle_orient2d_sign(const float a[3], const float b[3], const float c[3],
+                         int drop);
+
+/* Solid angle (steradians) of triangle (v0, v1, v2) seen from p.  Sets
+ * *on_tri = 1 (and returns 0) when p lies in the closed triangle. */
+double oracle_tri_solid_angle(const float p[3], const float v0[3], const float v1[3],
+                              const float v2[3], int *on_tri);
+
+/* Winding numbers of one surface at n points.
+ *   px, py, pz : float32 [n]           query points
+ *   verts      : float32 [n_vert][3]   surface vertices
+ *   tris       : int32 [n_tri][3]      counter-clockwise seen from outside
+ *   w          : double [n] out        Omega / (4 pi), compensated sum
+ *   on_surf    : uint8 [n] out or NULL 1 when p lies on the surface
+ * Uses n_threads host threads over point blocks (<= 0: all online cores). */
+void oracle_winding(int64_t n, const float *px, const float *py, const float *pz,
+                    int64_t n_vert, const float *verts, int64_t n_tri,
+                    const int32_t *tris, int n_threads, double *w, uint8_t *on_surf);
+
+/* Labels for n points against n_surf surfaces listed outermost first.
+ *   vert_off[s], tri_off[s] : offsets of surface s into verts / tris
+ *   (the tris of surface s index its own vertex block)
+ *   surf_label[s]           : compartment id of surface s
+ *   labels                  : int32 [n] out
+ *   w_out                   : double [n_surf][n] out, or NULL
+ * Returns the number of (point, surface) pairs evaluated. */
+int64_t oracle_label(int64_t n, const float *px, const float *py, const float *pz,
+                     int n_surf, const int64_t *vert_off, const int64_t *tri_off,
+                     const float *verts, const int32_t *tris,
+                     const int32_t *surf_label, double threshold, int n_threads,
+                     int32_t *labels, double *w_out);
+
+/* Independent inside test for a surface that is star-shaped about `center`:
+ * find the face whose cone (center, v0, v1, v2) holds p, then take the exact
+ * side of p against that face.  Returns 1 inside, 0 outside, 2 on the surface.
+ * Exact predicates only; O(n_tri) per point. */
+void oracle_radial_inside(int64_t n, const float *px, const float *py, const float *pz,
+                          const float center[3], const float *verts, int64_t n_tri,
+                          const int32_t *tris, int n_threads, uint8_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,176 @@
+"""Pins of the lattice / refinement oracle (paper sections 2.1.1-2.1.3) against
+exact integer geometry and brute force."""
+from fractions import Fraction
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import kuhn
+
+F32 = np.float32
+
+
+def _vol6(v):
+    """6 x signed volume of tetrahedra v [n, 4, 3] (exact for dyadic inputs)."""
+    a, b, c = v[:, 1] - v[:, 0], v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]
+    return np.einsum("ij,ij->i", a, np.cross(b, c))
+
+
+def test_six_tetrahedra_tile_the_cube():
+    keys = kuhn.level0_keys((1, 1, 1))
+    v = kuhn.vertices_units(keys)
+    vol6 = np.abs(_vol6(v))            # integer: 6 x volume
+    assert np.all(vol6 == 1.0) and vol6.sum() == 6.0
+    rng = np.random.default_rng(0)
+    y = rng.uniform(0, 1, (2000, 3))
+    k, inside = kuhn.locate(y, 0, (1, 1, 1))
+    assert inside.all()
+    # located tetrahedron really contains the point: all barycentric weights >= 0
+    for key, p in zip(k[:300], y[:300]):
+        t = kuhn.vertices_units(np.array([key], np.uint64))[0]
+        T = np.stack([t[1] - t[0], t[2] - t[0], t[3] - t[0]], 1)
+        lam = np.linalg.solve(T, p - t[0])
+        assert lam.min() > -1e-12 and lam.sum() < 1 + 1e-12
+
+
+def test_centroid_locates_back_to_its_tetrahedron():
+    rng = np.random.default_rng(1)
+    cells = (5, 4, 3)
+    for lv in range(3):
+        n = 500
+        keys = kuhn.encode(np.full(n, lv), rng.integers(0, 6, n),
+                           rng.integers(0, cells[0] << lv, n), rng.integers(0, cells[1] << lv, n),
+                           rng.integers(0, cells[2] << lv, n))
+        got, inside = kuhn.locate(kuhn.centroid_units(keys), lv, cells)
+        assert inside.all() and np.array_equal(got, keys)
+
+
+def test_children_are_the_red_refinement():
+    """Section 2.1.2: each refined element becomes 8 tetrahedra whose vertices
+    are the parent's vertices and edge midpoints, 1/8 of its volume each."""
+    for q in range(6):
+        key = kuhn.encode([0], [q], [0], [0], [0])
+        kids = kuhn.children(key, (1, 1, 1))[0]
+        assert len(set(kids.tolist())) == 8
+        pv = kuhn.vertices_units(key)[0]
+        allowed = {tuple(x) for x in pv}
+        for a, b in combinations(range(4), 2):
+            allowed.add(tuple((pv[a] + pv[b]) / 2))
+        kv = kuhn.vertices_units(kids)
+        for t in kv:
+            assert all(tuple(x) in allowed for x in t)
+        assert np.allclose(np.abs(_vol6(kv)), np.abs(_vol6(pv[None]))[0] / 8)
+        assert np.array_equal(kuhn.parent(kids, (1, 1, 1)), np.repeat(key, 8))
+
+
+def test_face_neighbour_shares_the_three_vertices():
+    rng = np.random.default_rng(2)
+    cells = (4, 4, 4)
+    keys = kuhn.level0_keys(cells)[rng.choice(384, 60, replace=False)]
+    v = kuhn.vertices_units(keys)
+    for t, key in zip(v, keys):
+        for m in range(4):
+            face = t[[x for x in range(4) if x != m]]
+            s = face.mean(0)
+            y = s + 2.0 ** -8 * (s - t[m])
+            nk, inside = kuhn.locate(y[None], 0, cells)
+            if not inside[0]:
+                continue
+            assert nk[0] != key
+            nv = {tuple(x) for x in kuhn.vertices_units(nk)[0]}
+            assert all(tuple(x) in nv for x in face)
+
+
+def _random_mesh(rng, cells, levels):
+    """Leaves of a random nested refinement, with random labels."""
+    leaves = list(kuhn.level0_keys(cells))
+    for _ in range(levels):
+        lv = kuhn.decode(np.array(leaves, np.uint64))[0]
+        cand = [k for k, l in zip(leaves, lv) if l == lv.max()]
+        pick = rng.choice(len(cand), max(1, len(cand) // 4), replace=False)
+        chosen = {cand[i] for i in pick}
+        kids = kuhn.children(np.array(sorted(chosen), np.uint64), cells).reshape(-1)
+        leaves = [k for k in leaves if k not in chosen] + list(kids)
+    keys = np.array(leaves, np.uint64)
+    return kuhn.LeafSet(keys, rng.integers(0, 3, len(keys)))
+
+
+def _bruteforce_boundary(ls):
+    """Two leaves touch in 2-D when a face of one and a face of the other are
+    coplanar, lie on opposite sides, and the centroid of the smaller face is
+    strictly inside the larger one (faces of nested Kuhn lattices are nested)."""
+    V = [[tuple(Fraction(x) for x in p) for p in t] for t in kuhn.vertices_units(ls.keys)]
+    faces = []
+    for ti, t in enumerate(V):
+        for m in range(4):
+            f = [t[x] for x in range(4) if x != m]
+            faces.append((ti, f, t[m]))
+
+    def sub(a, b):
+        return tuple(x - y for x, y in zip(a, b))
+
+    def cross(a, b):
+        return (a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0])
+
+    def dot(a, b):
+        return sum(x * y for x, y in zip(a, b))
+
+    def area2(f):
+        c = cross(sub(f[1], f[0]), sub(f[2], f[0]))
+        return dot(c, c)
+
+    def strictly_inside(g, f):
+        n = cross(sub(f[1], f[0]), sub(f[2], f[0]))
+        s = [dot(cross(sub(f[(i + 1) % 3], f[i]), sub(g, f[i])), n) for i in range(3)]
+        return all(x > 0 for x in s)
+
+    flag = np.zeros(len(V), bool)
+    for (ti, f, ot), (ui, g, ou) in combinations(faces, 2):
+        if ti == ui or ls.labels[ti] == ls.labels[ui]:
+            continue
+        n = cross(sub(f[1], f[0]), sub(f[2], f[0]))
+        if any(dot(n, sub(x, f[0])) != 0 for x in g):
+            continue
+        if dot(n, sub(ot, f[0])) * dot(n, sub(ou, f[0])) >= 0:
+            continue
+        small, big = (f, g) if area2(f) <= area2(g) else (g, f)
+        cen = tuple(sum(x[i] for x in small) / 3 for i in range(3))
+        if strictly_inside(cen, big):
+            flag[ti] = flag[ui] = True
+    return flag
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_boundary_marking_matches_bruteforce(seed):
+    rng = np.random.default_rng(seed)
+    cells = (2, 2, 1)
+    ls = _random_mesh(rng, cells, 2)
+    got = kuhn.boundary_mask(ls, cells, 2)
+    want = _bruteforce_boundary(ls)
+    assert np.array_equal(got, want)
+
+
+def test_refinement_counts_and_volume_partition():
+    cfg = synth.config_small("sphere", cells=8, subdiv=2)
+    lat = cfg.lattice
+    leaves, stats = kuhn.refine_relabel(lat, lambda p: oracle.label(p, cfg.surfaces), 2)
+    n0 = lat.n_points
+    assert stats[-1]["leaves"] == n0 + 7 * sum(s["boundary"] for s in stats)
+    assert len(leaves.keys) == stats[-1]["leaves"]
+    vol = np.abs(_vol6(kuhn.vertices_units(leaves.keys))).sum() / 6
+    assert vol == pytest.approx(np.prod(lat.cells), abs=1e-9)
+    # every leaf label is the label of its centroid
+    cen = kuhn.centroids_mm(leaves.keys, lat.origin, lat.h)
+    assert np.array_equal(oracle.label(cen, cfg.surfaces), leaves.labels)
+    assert stats[1]["boundary"] > 0 and stats[2]["boundary"] > 0
+
+
+def test_centroids_in_mm_are_exact_dyadics():
+    lat = synth.Lattice(origin=(-100.0, -100.0, -100.0), h=6.25, cells=(32, 32, 32))
+    keys = kuhn.level0_keys(lat.cells)[:5000]
+    c = kuhn.centroids_mm(keys, lat.origin, lat.h).astype(np.float64)
+    ref = np.array(lat.origin)[:, None] + lat.h * kuhn.centroid_units(keys).T
+    assert np.array_equal(c, ref)
