@@ -1,0 +1,248 @@
+/*
+ * sal.h -- solid-angle labeling of tetrahedral lattices on AMD Instinct MI355X
+ * (gfx950).  C ABI; every entry point is noexcept and reports through
+ * sal_status.
+ *
+ * The method (paper "Multi-compartment human head modeling: generating
+ * adaptive tetrahedral mesh with GPU acceleration", section 2.1):
+ *   - a regular hexahedral lattice fills the domain; each hexahedron is split
+ *     into tetrahedra (section 2.1.1; this library uses the six-tetrahedron
+ *     Kuhn split of Fig. 1c);
+ *   - a point is labeled with the solid-angle method (section 2.1.3, Eq. 1):
+ *     s = Omega_S(p) / (4 pi) is the winding number of the closed surface S at
+ *     p; p is enclosed by S when s >= T;
+ *   - compartments are nested and, where boundaries intersect, the surface
+ *     first in the hierarchy wins; a bounding box is the outermost compartment
+ *     (section 2.1);
+ *   - elements on a label boundary are refined 1 -> 8 (section 2.1.2, Fig. 2)
+ *     and only the new elements are labeled again, recursively (section
+ *     2.1.3 item 2, Fig. 3).
+ *
+ * Conventions shared by all calls
+ *   - Coordinates are float32 millimetres; they are promoted exactly to double
+ *     wherever double precision is used.
+ *   - Surfaces are closed, consistently oriented triangle meshes whose
+ *     triangles are counter-clockwise seen from outside (outward normals), so
+ *     the winding number is +1 inside.  They are given outermost first: a
+ *     later surface has higher priority ("first in the hierarchy") and wins
+ *     where several enclose a point.  Label 0 is the bounding box.
+ *   - A point lying exactly on a surface counts as enclosed by it.
+ *   - Device pointers are HIP device (or managed) memory owned by the caller;
+ *     they must stay valid until the work enqueued on the context's stream
+ *     has finished.  Host pointers are read during the call only.
+ *   - Work is enqueued on the context's stream and the call returns without
+ *     waiting, unless a stats pointer is given (then the call synchronises
+ *     the stream to fill it) or the entry point says otherwise.
+ *   - On any error nothing further is enqueued; outputs are unspecified.
+ *     sal_last_error_message() returns a thread-local description of the
+ *     last error on the calling thread.
+ *   - Nothing in this library runs on the CPU except argument checking,
+ *     surface preprocessing (validation, triangle strips) and launch logic.
+ */
+#ifndef SAL_H
+#define SAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SAL_ABI_VERSION 1
+
+typedef enum sal_status {
+    SAL_OK = 0,
+    SAL_ERR_INVALID_ARG = 1,   /* NULL pointer, bad size, bad option, NaN input */
+    SAL_ERR_NOT_CLOSED = 2,    /* a surface is not a closed 2-manifold */
+    SAL_ERR_ORIENTATION = 3,   /* a surface encloses negative volume (inward faces) */
+    SAL_ERR_OUT_OF_MEMORY = 4, /* device or host allocation failed */
+    SAL_ERR_DEVICE = 5,        /* HIP runtime error, or no usable device */
+    SAL_ERR_CAPACITY = 6,      /* a size limit of this library was exceeded */
+    SAL_ERR_INTERNAL = 7
+} sal_status;
+
+/* Static description of a status code. */
+const char *sal_status_string(sal_status s);
+/* Description of the last failure on this thread (empty if none). */
+const char *sal_last_error_message(void);
+/* SAL_ABI_VERSION of the loaded library. */
+int sal_abi_version(void);
+
+typedef struct sal_context sal_context;
+typedef struct sal_surface_set sal_surface_set;
+typedef struct sal_tet_mesh sal_tet_mesh;
+
+/* ------------------------------------------------------------------ context
+ * Binds a device and a stream.  hip_stream is a hipStream_t (NULL = the
+ * default stream).  The context owns its scratch memory; it is not
+ * thread-safe (use one context per host thread). */
+sal_status sal_context_create(int device, void *hip_stream, sal_context **out);
+sal_status sal_context_set_stream(sal_context *ctx, void *hip_stream);
+void sal_context_destroy(sal_context *ctx); /* NULL-safe; waits for the stream */
+
+/* ------------------------------------------------------------- surface set
+ * The closed segmentation surfaces of section 2.1 in hierarchy order
+ * (outermost first).  Creation validates every surface, builds triangle
+ * strips and copies the geometry to the device (float32 strip records plus a
+ * float64 copy for the recheck and plain-FP64 forms).  The set owns its
+ * device memory and does not reference the descriptors after the call.
+ *
+ * Errors: SAL_ERR_INVALID_ARG (NULL, n_surfaces outside 1..64, an index out
+ * of range, a repeated vertex in a triangle, a zero-area triangle, a
+ * non-finite coordinate, label <= 0), SAL_ERR_NOT_CLOSED (some directed edge
+ * appears twice or lacks its reverse), SAL_ERR_ORIENTATION (negative enclosed
+ * volume and SAL_SURF_AUTO_ORIENT not set). */
+typedef struct sal_surface_desc {
+    int64_t n_vertices;
+    const float *xyz;      /* host [n_vertices][3] */
+    int64_t n_triangles;
+    const int32_t *tri;    /* host [n_triangles][3], counter-clockwise from outside */
+    int32_t label;         /* compartment id, > 0 */
+} sal_surface_desc;
+
+#define SAL_SURF_AUTO_ORIENT 1u /* reverse surfaces that enclose negative volume */
+
+sal_status sal_surface_set_create(sal_context *ctx, const sal_surface_desc *surfaces,
+                                  int32_t n_surfaces, uint32_t flags,
+                                  sal_surface_set **out);
+void sal_surface_set_destroy(sal_surface_set *set); /* NULL-safe */
+
+typedef struct sal_surface_set_info {
+    int32_t n_surfaces;
+    int64_t n_triangles;   /* total over all surfaces */
+    int64_t n_strips;      /* triangle strips built at creation */
+    int64_t device_bytes;  /* device memory held by the set */
+} sal_surface_set_info;
+sal_status sal_surface_set_get_info(const sal_surface_set *set, sal_surface_set_info *info);
+
+/* ----------------------------------------------------------------- labeling
+ * Precision forms of the pair loop:
+ *   SAL_PREC_FP64          every (point, triangle) solid angle in double, with
+ *                          an exact sign of the triple product where double
+ *                          cannot certify it ("plain FP64");
+ *   SAL_PREC_FP32_RECHECK  solid angles in float32, summed per strip and
+ *                          accumulated in double; a (point, surface) pair is
+ *                          recomputed in the FP64 form when |w - T| <
+ *                          recheck_band or when any of its triangles is
+ *                          ill-conditioned in float32 (see kappa).  Labels are
+ *                          those of the FP64 form. */
+enum { SAL_PREC_FP64 = 0, SAL_PREC_FP32_RECHECK = 1 };
+enum { SAL_WINDING_NONE = 0, SAL_WINDING_F32 = 1, SAL_WINDING_F64 = 2 };
+
+typedef struct sal_label_options {
+    int32_t precision;        /* SAL_PREC_* (default SAL_PREC_FP32_RECHECK) */
+    int32_t winding_type;     /* SAL_WINDING_* for the optional winding output */
+    double threshold;         /* T of section 2.1.3, in (0, 1); default 0.5 */
+    double recheck_band;      /* default 1e-3 */
+    double kappa;             /* float32 conditioning threshold; 0 = 2^-5 */
+    int32_t points_per_lane;  /* 0 = tuned; else 1, 2 or 4 */
+    int32_t block_waves;      /* 0 = tuned; else 1, 2, 4 or 8 wavefronts per block */
+} sal_label_options;
+
+/* Fills the defaults listed above. */
+void sal_label_options_default(sal_label_options *opt);
+
+typedef struct sal_label_stats {
+    int64_t n_points;
+    int64_t n_pairs;           /* n_points x total triangles (nominal) */
+    int64_t n_recheck_points;  /* points with at least one FP64-rechecked surface */
+    int64_t n_recheck_pairs;   /* (point, surface) pairs rechecked in FP64 */
+    int64_t n_band_flags;      /* pairs flagged by |w - T| < recheck_band */
+    int64_t n_cond_flags;      /* pairs flagged by an ill-conditioned triangle */
+    int64_t n_exact_fallbacks; /* triangle evaluations that needed the exact sign */
+    float ms_pairloop;         /* device time of the pair loop */
+    float ms_recheck;          /* device time of the FP64 recheck */
+    float ms_total;            /* device time from first to last kernel */
+} sal_label_stats;
+
+/* Labels n_points points (section 2.1.3: s = Omega / 4 pi, enclosed when
+ * s >= T or on the surface; section 2.1: the highest-priority enclosing
+ * surface gives the label, else 0).
+ *   x, y, z  device float32 [n_points] (SoA)
+ *   labels   device int32 [n_points] out; -1 for a point with a non-finite
+ *            coordinate
+ *   winding  device [n_surfaces][n_points] of float (SAL_WINDING_F32) or
+ *            double (SAL_WINDING_F64), or NULL; receives w per surface
+ *   opt      NULL = defaults
+ *   stats    NULL, or filled after synchronising the stream
+ * n_points == 0 is valid and enqueues nothing. */
+sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_t n_points,
+                            const float *x, const float *y, const float *z,
+                            const sal_label_options *opt, int32_t *labels, void *winding,
+                            sal_label_stats *stats);
+
+/* ----------------------------------------------------------- tetrahedral mesh
+ * A Kuhn lattice (section 2.1.1) with nested red refinement (section 2.1.2).
+ *
+ * Geometry, in lattice units u = (x - origin) / h:
+ *   level-0 cell (i, j, k) is the cube [i, i+1] x [j, j+1] x [k, k+1]; it
+ *   holds six tetrahedra, one per permutation pi of the axes, q = index of pi
+ *   in the lexicographic list (x,y,z), (x,z,y), (y,x,z), (y,z,x), (z,x,y),
+ *   (z,y,x):  {u : 1 >= f[pi0] >= f[pi1] >= f[pi2] >= 0}, f = u - cell;
+ *   level l uses cells of edge h 2^-l; the 8 children of a tetrahedron are
+ *   the level-(l+1) tetrahedra inside it (red refinement).
+ * Centroid, computed in double and rounded once to float32:
+ *   x_a = origin_a + (h 2^-l) (cell_a + c_a), c[pi0] = 3/4, c[pi1] = 1/2,
+ *   c[pi2] = 1/4.
+ * Key (uint64): l << 60 | q << 57 | i << 38 | j << 19 | k (i, j, k < 2^19).
+ * Level-0 leaves are numbered ((k ny + j) nx + i) 6 + q.
+ *
+ * Creation allocates the level-0 leaves (unlabeled).  Limits: cells in
+ * 1..2^19 >> 3 per axis (so three refinement levels fit in 19 bits), at most
+ * 3 refinement levels. */
+sal_status sal_tet_mesh_create_lattice(sal_context *ctx, const double origin[3], double h,
+                                       const int32_t cells[3], sal_tet_mesh **out);
+void sal_tet_mesh_destroy(sal_tet_mesh *mesh); /* NULL-safe */
+
+typedef struct sal_refine_stats {
+    int64_t n_leaves;     /* leaves after this round */
+    int64_t n_boundary;   /* leaves split this round (0 for round 0) */
+    int64_t n_labeled;    /* points labeled this round */
+    int64_t n_pairs;      /* n_labeled x total triangles */
+    int64_t n_recheck_pairs;
+    float ms_mark, ms_compact, ms_split, ms_label, ms_total;
+} sal_refine_stats;
+
+/* Section 2.1.3: labels every unlabeled leaf (round 0: the whole lattice),
+ * then `rounds` times: marks each leaf sharing a 2-D part of a face with a
+ * leaf of another label (faces on the domain boundary ignored), splits the
+ * marked leaves 1 -> 8 and labels only the children.
+ *   per_round  NULL, or [rounds + 1] filled after synchronising
+ * Synchronises the stream once per round to size the new level.  Errors:
+ * SAL_ERR_CAPACITY when a leaf would exceed refinement level 3. */
+sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *mesh, const sal_surface_set *set,
+                              int32_t rounds, const sal_label_options *opt,
+                              sal_refine_stats *per_round);
+
+/* Number of leaves and the deepest level present. */
+sal_status sal_tet_mesh_size(const sal_tet_mesh *mesh, int64_t *n_leaves, int32_t *max_level);
+
+/* Copies the leaves, ordered by level then by position within the level,
+ * into caller device buffers [n_leaves] (each may be NULL):
+ *   keys (uint64), labels (int32; -2 for a leaf not labeled yet),
+ *   cx, cy, cz (float32 centroids). */
+sal_status sal_tet_mesh_export(sal_context *ctx, const sal_tet_mesh *mesh, uint64_t *keys,
+                               int32_t *labels, float *cx, float *cy, float *cz);
+
+/* ------------------------------------------------------------ batched form
+ * Many independent labeling problems in one persistent launch: the work is
+ * cut into (instance, point block, surface, triangle range) items ordered by
+ * cost, pulled by resident workgroups from a device counter; partial winding
+ * sums are reduced per (point, surface) in a fixed order; one FP64 recheck
+ * pass serves all instances.  Labels equal those of sal_label_points on each
+ * instance.  Each instance's arrays follow the rules of sal_label_points.
+ *   per_instance  NULL, or [n_inst] stats filled after synchronising */
+typedef struct sal_instance {
+    const sal_surface_set *surfaces;
+    int64_t n_points;
+    const float *x, *y, *z; /* device float32 [n_points] */
+    int32_t *labels;        /* device int32 [n_points] out */
+} sal_instance;
+
+sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst, int32_t n_inst,
+                           const sal_label_options *opt, sal_label_stats *per_instance);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAL_H */

@@ -1,0 +1,268 @@
+// C-ABI entry points: contexts, surface sets, point labeling.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "runtime.h"
+
+namespace sal {
+
+static thread_local std::string g_last_error;
+
+sal_status set_error(sal_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+sal_status hip_error(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? SAL_ERR_OUT_OF_MEMORY : SAL_ERR_DEVICE;
+}
+
+sal_status ensure_flag_capacity(sal_context *ctx, int64_t n) {
+    if (n <= ctx->flag_cap) return SAL_OK;
+    SAL_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->flag_list) SAL_HIP(hipFree(ctx->flag_list));
+    ctx->flag_list = nullptr;
+    ctx->flag_cap = 0;
+    const int64_t cap = n < 4096 ? 4096 : n;
+    SAL_HIP(hipMalloc((void **)&ctx->flag_list, (size_t)cap * sizeof(FlagEntry)));
+    ctx->flag_cap = cap;
+    return SAL_OK;
+}
+
+sal_status resolve_options(const sal_label_options *in, sal_label_options *out) {
+    sal_label_options_default(out);
+    if (in) *out = *in;
+    if (out->precision != SAL_PREC_FP64 && out->precision != SAL_PREC_FP32_RECHECK)
+        return set_error(SAL_ERR_INVALID_ARG, "precision must be SAL_PREC_FP64 or SAL_PREC_FP32_RECHECK");
+    if (out->winding_type < SAL_WINDING_NONE || out->winding_type > SAL_WINDING_F64)
+        return set_error(SAL_ERR_INVALID_ARG, "bad winding_type");
+    if (!(out->threshold > 0.0 && out->threshold < 1.0))
+        return set_error(SAL_ERR_INVALID_ARG, "threshold must be in (0, 1)");
+    if (!(out->recheck_band >= 0.0 && out->recheck_band < 1.0))
+        return set_error(SAL_ERR_INVALID_ARG, "recheck_band must be in [0, 1)");
+    if (out->kappa == 0.0) out->kappa = 0.03125;
+    if (!(out->kappa > 0.0 && out->kappa < 1.0))
+        return set_error(SAL_ERR_INVALID_ARG, "kappa must be in (0, 1)");
+    if (out->points_per_lane == 0) out->points_per_lane = 2;
+    if (out->points_per_lane != 1 && out->points_per_lane != 2 && out->points_per_lane != 4)
+        return set_error(SAL_ERR_INVALID_ARG, "points_per_lane must be 0, 1, 2 or 4");
+    if (out->block_waves == 0) out->block_waves = 4;
+    if (out->block_waves != 1 && out->block_waves != 2 && out->block_waves != 4 &&
+        out->block_waves != 8)
+        return set_error(SAL_ERR_INVALID_ARG, "block_waves must be 0, 1, 2, 4 or 8");
+    return SAL_OK;
+}
+
+sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
+                         const float *y, const float *z, const sal_label_options &opt,
+                         int32_t *labels, void *winding, hipEvent_t ev_mid) {
+    PairloopArgs a{};
+    a.rec32 = set->rec32;
+    a.rec64 = set->rec64;
+    a.surf = set->surf;
+    a.n_surf = set->n_surf;
+    a.x = x;
+    a.y = y;
+    a.z = z;
+    a.n = n;
+    a.kappa = (float)opt.kappa;
+    a.threshold = opt.threshold;
+    a.band = opt.recheck_band;
+    a.labels = labels;
+    a.winding = winding;
+    a.winding_type = winding ? opt.winding_type : SAL_WINDING_NONE;
+    if (!winding) a.winding = nullptr;
+    a.flag_list = ctx->flag_list;
+    a.counters = ctx->counters;
+    if (opt.precision == SAL_PREC_FP64) {
+        SAL_HIP(launch_pairloop_f64(a, opt.block_waves, ctx->stream));
+        if (ev_mid) SAL_HIP(hipEventRecord(ev_mid, ctx->stream));
+        return SAL_OK;
+    }
+    SAL_HIP(launch_pairloop_f32(a, opt.points_per_lane, opt.block_waves, ctx->stream));
+    if (ev_mid) SAL_HIP(hipEventRecord(ev_mid, ctx->stream));
+    RecheckArgs r{};
+    r.rec64 = set->rec64;
+    r.surf = set->surf;
+    r.strip_off = set->strip_off;
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.n = n;
+    r.threshold = opt.threshold;
+    r.labels = labels;
+    r.winding = a.winding;
+    r.winding_type = a.winding_type;
+    r.flag_list = ctx->flag_list;
+    r.counters = ctx->counters;
+    const int64_t grid = n < (int64_t)ctx->n_cu * 8 ? n : (int64_t)ctx->n_cu * 8;
+    SAL_HIP(launch_recheck_f64(r, (int)grid, ctx->stream));
+    return SAL_OK;
+}
+
+}  // namespace sal
+
+using namespace sal;
+
+#define SAL_GUARD_BEGIN try {
+#define SAL_GUARD_END                                                          \
+    }                                                                          \
+    catch (const std::bad_alloc &) {                                           \
+        return set_error(SAL_ERR_OUT_OF_MEMORY, "host allocation failed");     \
+    }                                                                          \
+    catch (const std::exception &ex) {                                         \
+        return set_error(SAL_ERR_INTERNAL, ex.what());                         \
+    }                                                                          \
+    catch (...) {                                                              \
+        return set_error(SAL_ERR_INTERNAL, "unknown exception");               \
+    }
+
+extern "C" {
+
+const char *sal_status_string(sal_status s) {
+    switch (s) {
+        case SAL_OK: return "ok";
+        case SAL_ERR_INVALID_ARG: return "invalid argument";
+        case SAL_ERR_NOT_CLOSED: return "surface not closed";
+        case SAL_ERR_ORIENTATION: return "surface orientation";
+        case SAL_ERR_OUT_OF_MEMORY: return "out of memory";
+        case SAL_ERR_DEVICE: return "device error";
+        case SAL_ERR_CAPACITY: return "capacity exceeded";
+        case SAL_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char *sal_last_error_message(void) { return g_last_error.c_str(); }
+
+int sal_abi_version(void) { return SAL_ABI_VERSION; }
+
+void sal_label_options_default(sal_label_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = SAL_PREC_FP32_RECHECK;
+    o->winding_type = SAL_WINDING_NONE;
+    o->threshold = 0.5;
+    o->recheck_band = 1e-3;
+    o->kappa = 0.0;
+    o->points_per_lane = 0;
+    o->block_waves = 0;
+}
+
+sal_status sal_context_create(int device, void *stream, sal_context **out) {
+    SAL_GUARD_BEGIN
+    g_last_error.clear();
+    if (!out) return set_error(SAL_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return set_error(SAL_ERR_DEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return set_error(SAL_ERR_INVALID_ARG, "device out of range");
+    SAL_HIP(hipSetDevice(device));
+    auto *ctx = new sal_context();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
+    if (ctx->n_cu <= 0) ctx->n_cu = 256;
+    for (auto &ev : ctx->ev) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipEventCreate"); }
+    }
+    e = hipMalloc((void **)&ctx->counters, kNumCounters * sizeof(unsigned long long));
+    if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(counters)"); }
+    *out = ctx;
+    return SAL_OK;
+    SAL_GUARD_END
+}
+
+sal_status sal_context_set_stream(sal_context *ctx, void *stream) {
+    if (!ctx) return set_error(SAL_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->stream = (hipStream_t)stream;
+    return SAL_OK;
+}
+
+void sal_context_destroy(sal_context *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &ev : ctx->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (ctx->flag_list) (void)hipFree(ctx->flag_list);
+    if (ctx->counters) (void)hipFree(ctx->counters);
+    delete ctx;
+}
+
+sal_status sal_surface_set_create(sal_context *ctx, const sal_surface_desc *s, int32_t n,
+                                  uint32_t flags, sal_surface_set **out) {
+    SAL_GUARD_BEGIN
+    g_last_error.clear();
+    if (out) *out = nullptr;
+    if (flags & ~SAL_SURF_AUTO_ORIENT) return set_error(SAL_ERR_INVALID_ARG, "unknown flag bits");
+    return build_surface_set(ctx, s, n, flags, out);
+    SAL_GUARD_END
+}
+
+void sal_surface_set_destroy(sal_surface_set *set) { destroy_surface_set(set); }
+
+sal_status sal_surface_set_get_info(const sal_surface_set *set, sal_surface_set_info *info) {
+    if (!set || !info) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+    info->n_surfaces = set->n_surf;
+    info->n_triangles = set->n_tri;
+    info->n_strips = set->n_strips;
+    info->device_bytes = set->bytes;
+    return SAL_OK;
+}
+
+sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_t n,
+                            const float *x, const float *y, const float *z,
+                            const sal_label_options *opt_in, int32_t *labels, void *winding,
+                            sal_label_stats *stats) {
+    SAL_GUARD_BEGIN
+    g_last_error.clear();
+    if (!ctx || !set) return set_error(SAL_ERR_INVALID_ARG, "ctx or set is NULL");
+    if (n < 0) return set_error(SAL_ERR_INVALID_ARG, "n_points < 0");
+    if (set->device != ctx->device)
+        return set_error(SAL_ERR_INVALID_ARG, "surface set lives on another device");
+    sal_label_options opt;
+    sal_status st = resolve_options(opt_in, &opt);
+    if (st != SAL_OK) return st;
+    if (winding && opt.winding_type == SAL_WINDING_NONE)
+        return set_error(SAL_ERR_INVALID_ARG, "winding buffer given with SAL_WINDING_NONE");
+    if (n > 0 && (!x || !y || !z || !labels))
+        return set_error(SAL_ERR_INVALID_ARG, "NULL point or label buffer");
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (n == 0) return SAL_OK;
+    SAL_HIP(hipSetDevice(ctx->device));
+    if (opt.precision == SAL_PREC_FP32_RECHECK) {
+        st = ensure_flag_capacity(ctx, n);
+        if (st != SAL_OK) return st;
+    }
+    SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, ctx->stream));
+    if (stats) SAL_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+    st = enqueue_label(ctx, set, n, x, y, z, opt, labels, winding, stats ? ctx->ev[1] : nullptr);
+    if (st != SAL_OK) return st;
+    if (stats) {
+        SAL_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
+        SAL_HIP(hipEventSynchronize(ctx->ev[2]));
+        unsigned long long c[kNumCounters];
+        SAL_HIP(hipMemcpy(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost));
+        stats->n_points = n;
+        stats->n_pairs = n * set->n_tri;
+        stats->n_recheck_points = (int64_t)c[kCntFlagged];
+        stats->n_recheck_pairs = (int64_t)c[kCntRecheck];
+        stats->n_band_flags = (int64_t)c[kCntBand];
+        stats->n_cond_flags = (int64_t)c[kCntCond];
+        stats->n_exact_fallbacks = (int64_t)c[kCntExact];
+        SAL_HIP(hipEventElapsedTime(&stats->ms_pairloop, ctx->ev[0], ctx->ev[1]));
+        SAL_HIP(hipEventElapsedTime(&stats->ms_total, ctx->ev[0], ctx->ev[2]));
+        stats->ms_recheck = stats->ms_total - stats->ms_pairloop;
+    }
+    return SAL_OK;
+    SAL_GUARD_END
+}
+
+}  // extern "C"

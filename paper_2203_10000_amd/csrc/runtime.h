@@ -1,0 +1,49 @@
+// Host-side objects behind the opaque handles of sal.h.
+#pragma once
+
+#include <vector>
+
+#include "sal_internal.h"
+
+// Device scratch owned by a context; grows, never shrinks.
+struct sal_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[8] = {};
+    sal::FlagEntry *flag_list = nullptr;
+    int64_t flag_cap = 0;
+    unsigned long long *counters = nullptr;  // sal::kNumCounters
+    int n_cu = 0;
+};
+
+struct sal_surface_set {
+    int device = 0;
+    int n_surf = 0;
+    int64_t n_tri = 0, n_strips = 0, n_rec = 0, bytes = 0;
+    sal::Rec32 *rec32 = nullptr;
+    sal::Rec64 *rec64 = nullptr;
+    sal::SurfaceDev *surf = nullptr;
+    int64_t *strip_off = nullptr;
+    std::vector<sal::SurfaceDev> host_table;
+};
+
+namespace sal {
+
+sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int32_t n,
+                             uint32_t flags, sal_surface_set **out);
+void destroy_surface_set(sal_surface_set *set);
+
+// Grows the context scratch to hold a flag list of n entries.
+sal_status ensure_flag_capacity(sal_context *ctx, int64_t n);
+
+// Validated options with defaults applied.
+sal_status resolve_options(const sal_label_options *in, sal_label_options *out);
+
+// Enqueues one labeling pass (pair loop, and recheck in the float32 form) of
+// n points; counters must be cleared by the caller.  Records events ev_a
+// (after the pair loop) when non-null.
+sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
+                         const float *y, const float *z, const sal_label_options &opt,
+                         int32_t *labels, void *winding, hipEvent_t ev_after_pairloop);
+
+}  // namespace sal

@@ -1,0 +1,127 @@
+// Internal declarations shared by the host runtime (*.cpp) and the gfx950
+// kernels (*.hip) of libsal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sal.h"
+
+namespace sal {
+
+// ---------------------------------------------------------------- records
+// A surface is stored as triangle strips.  A strip with vertices
+// v0, v1, ..., v_{m+1} holds the m triangles (v_i, v_{i+1}, v_{i+2}); the two
+// last vertices of one triangle are the two first of the next, so the
+// per-vertex terms (v - p, |v - p|) and the dot product of the shared edge
+// are computed once per strip step instead of once per triangle.
+//
+// float32 stream, 32 bytes per record, read by every lane of a wavefront at
+// the same address (scalar loads, broadcast through SGPRs):
+//   head: { x0, y0, z0, x1, y1, z1, bits(m), 0 }
+//   tri : { x, y, z,  16 nx, 16 ny, 16 nz,  |n|,  KN_SMALL |n| }
+// where (x, y, z) is the strip's next vertex and n = (B - A) x (C - A) is the
+// outward (unnormalised) normal of the original triangle (A, B, C), computed in
+// double from the float32 vertices and rounded once.  The factor 16 is a power
+// of two (exact) that folds the small-angle bound |N/D| < 1/16 into one
+// comparison.
+struct alignas(32) Rec32 {
+    float v[8];
+};
+
+// float64 stream, same record order, 64 bytes per record:
+//   head: { x0, y0, z0, x1, y1, z1, bits(m), 0 }
+//   tri : { x, y, z,  nx, ny, nz,  |B - A| |C - A|,  sigma }
+// sigma = +1 when the strip order (v_i, v_{i+1}, v_{i+2}) is an even
+// permutation of (A, B, C), -1 otherwise; it orients the exact predicate.
+struct alignas(64) Rec64 {
+    double v[8];
+};
+
+constexpr float kNScale = 16.0f;     // normal pre-scale in the float32 stream
+constexpr float kKnSmall = 5.0f;     // small-angle path needs D > 5 |n| r_Z + ...
+constexpr int kMaxSurfaces = 64;     // per-point masks are 64-bit
+
+// Per-surface table in device memory.
+struct SurfaceDev {
+    int64_t rec_begin, rec_end;      // [begin, end) in both record streams
+    int64_t strip_begin, strip_end;  // [begin, end) in the strip table
+    int64_t n_tri;
+    int32_t label;
+    int32_t pad;
+};
+
+// A point with at least one (surface) winding number that the float32 pass
+// cannot certify.
+struct FlagEntry {
+    int64_t idx;     // point index
+    uint64_t enc;    // bit k: float32 pass found w_k >= T
+    uint64_t flg;    // bit k: surface k must be recomputed in FP64
+};
+
+// Device counters (uint64) of one labeling call.
+enum Counter {
+    kCntFlagged = 0,   // entries appended to the flag list
+    kCntBand = 1,      // (point, surface) pairs flagged by the band
+    kCntCond = 2,      // pairs flagged by ill-conditioned triangles
+    kCntExact = 3,     // exact-sign evaluations
+    kCntRecheck = 4,   // pairs recomputed in FP64
+    kNumCounters = 8
+};
+
+struct PairloopArgs {
+    const Rec32 *__restrict__ rec32;
+    const Rec64 *__restrict__ rec64;
+    const SurfaceDev *__restrict__ surf;
+    int n_surf;
+    const float *__restrict__ x;
+    const float *__restrict__ y;
+    const float *__restrict__ z;
+    int64_t n;
+    float kappa;
+    double threshold;
+    double band;
+    int32_t *__restrict__ labels;
+    void *__restrict__ winding;   // [n_surf][n] float or double, or null
+    int winding_type;
+    FlagEntry *__restrict__ flag_list;  // capacity n
+    unsigned long long *__restrict__ counters;
+};
+
+struct RecheckArgs {
+    const Rec64 *__restrict__ rec64;
+    const SurfaceDev *__restrict__ surf;
+    const int64_t *__restrict__ strip_off;  // record index of every strip head
+    const float *__restrict__ x;
+    const float *__restrict__ y;
+    const float *__restrict__ z;
+    int64_t n;
+    double threshold;
+    int32_t *__restrict__ labels;
+    void *__restrict__ winding;
+    int winding_type;
+    const FlagEntry *__restrict__ flag_list;
+    unsigned long long *__restrict__ counters;
+};
+
+// Kernel launchers (pairloop.hip, recheck.hip).
+hipError_t launch_pairloop_f32(const PairloopArgs &a, int points_per_lane, int block_waves,
+                               hipStream_t s);
+hipError_t launch_pairloop_f64(const PairloopArgs &a, int block_waves, hipStream_t s);
+hipError_t launch_recheck_f64(const RecheckArgs &a, int grid_blocks, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------ host helpers
+sal_status set_error(sal_status s, const std::string &msg);
+sal_status hip_error(hipError_t e, const char *what);
+
+}  // namespace sal
+
+#define SAL_HIP(expr)                                             \
+    do {                                                          \
+        hipError_t _e = (expr);                                   \
+        if (_e != hipSuccess) return ::sal::hip_error(_e, #expr); \
+    } while (0)

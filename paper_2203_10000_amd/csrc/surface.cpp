@@ -1,0 +1,291 @@
+// Surface-set construction: validation of closed oriented manifolds, greedy
+// triangle strips, float32 / float64 strip records on the device.
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "runtime.h"
+
+namespace sal {
+
+namespace {
+
+inline uint64_t edge_key(uint32_t a, uint32_t b) { return ((uint64_t)a << 32) | b; }
+
+struct HostSurface {
+    const float *xyz;
+    int64_t nv, nt;
+    std::vector<int32_t> tri;  // possibly reoriented copy
+    int32_t label;
+};
+
+// One strip: the vertex sequence and, per triangle, its index in the surface.
+struct Strip {
+    std::vector<int32_t> verts;
+    std::vector<int32_t> tris;
+};
+
+sal_status validate(HostSurface &s, int idx, bool auto_orient) {
+    const std::string who = "surface " + std::to_string(idx) + ": ";
+    if (s.nv < 3 || s.nt < 4 || !s.xyz || s.tri.empty())
+        return set_error(SAL_ERR_INVALID_ARG, who + "needs >= 3 vertices and >= 4 triangles");
+    if (s.label <= 0) return set_error(SAL_ERR_INVALID_ARG, who + "label must be > 0");
+    if (s.nt > (int64_t)1 << 30 || s.nv > (int64_t)1 << 30)
+        return set_error(SAL_ERR_CAPACITY, who + "more than 2^30 vertices or triangles");
+    for (int64_t i = 0; i < 3 * s.nv; ++i)
+        if (!std::isfinite(s.xyz[i]))
+            return set_error(SAL_ERR_INVALID_ARG, who + "non-finite vertex coordinate");
+    std::unordered_map<uint64_t, int64_t> dir;
+    dir.reserve((size_t)(3 * s.nt * 2));
+    for (int64_t t = 0; t < s.nt; ++t) {
+        const int32_t *f = &s.tri[3 * t];
+        for (int c = 0; c < 3; ++c)
+            if (f[c] < 0 || f[c] >= s.nv)
+                return set_error(SAL_ERR_INVALID_ARG, who + "vertex index out of range");
+        if (f[0] == f[1] || f[1] == f[2] || f[0] == f[2])
+            return set_error(SAL_ERR_INVALID_ARG, who + "triangle repeats a vertex");
+        const float *A = s.xyz + 3 * f[0], *B = s.xyz + 3 * f[1], *C = s.xyz + 3 * f[2];
+        const double e1[3] = {(double)B[0] - A[0], (double)B[1] - A[1], (double)B[2] - A[2]};
+        const double e2[3] = {(double)C[0] - A[0], (double)C[1] - A[1], (double)C[2] - A[2]};
+        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+        if (n[0] == 0.0 && n[1] == 0.0 && n[2] == 0.0)
+            return set_error(SAL_ERR_INVALID_ARG, who + "zero-area triangle");
+        for (int c = 0; c < 3; ++c) {
+            const uint64_t k = edge_key((uint32_t)f[c], (uint32_t)f[(c + 1) % 3]);
+            if (!dir.emplace(k, t).second)
+                return set_error(SAL_ERR_NOT_CLOSED, who + "a directed edge is used twice");
+        }
+    }
+    for (const auto &kv : dir) {
+        const uint32_t a = (uint32_t)(kv.first >> 32), b = (uint32_t)kv.first;
+        if (!dir.count(edge_key(b, a)))
+            return set_error(SAL_ERR_NOT_CLOSED, who + "boundary edge (surface is open)");
+    }
+    // enclosed volume, about the vertex centroid for accuracy
+    double c[3] = {0, 0, 0};
+    for (int64_t i = 0; i < s.nv; ++i)
+        for (int d = 0; d < 3; ++d) c[d] += s.xyz[3 * i + d];
+    for (int d = 0; d < 3; ++d) c[d] /= (double)s.nv;
+    double vol = 0.0;
+    for (int64_t t = 0; t < s.nt; ++t) {
+        const int32_t *f = &s.tri[3 * t];
+        double v[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int d = 0; d < 3; ++d) v[r][d] = (double)s.xyz[3 * f[r] + d] - c[d];
+        vol += v[0][0] * (v[1][1] * v[2][2] - v[1][2] * v[2][1]) +
+               v[0][1] * (v[1][2] * v[2][0] - v[1][0] * v[2][2]) +
+               v[0][2] * (v[1][0] * v[2][1] - v[1][1] * v[2][0]);
+    }
+    if (!(vol != 0.0)) return set_error(SAL_ERR_ORIENTATION, who + "encloses zero volume");
+    if (vol < 0.0) {
+        if (!auto_orient)
+            return set_error(SAL_ERR_ORIENTATION,
+                             who + "triangles are clockwise seen from outside (negative volume)");
+        for (int64_t t = 0; t < s.nt; ++t) std::swap(s.tri[3 * t + 1], s.tri[3 * t + 2]);
+    }
+    return SAL_OK;
+}
+
+// Greedy strips: from each unused seed triangle try the three rotations,
+// walk across the edge formed by the two newest vertices while the next
+// triangle is unused, and keep the longest walk.
+std::vector<Strip> make_strips(const HostSurface &s) {
+    const int64_t nt = s.nt;
+    std::unordered_map<uint64_t, int32_t> dir;
+    dir.reserve((size_t)(3 * nt * 2));
+    for (int64_t t = 0; t < nt; ++t)
+        for (int c = 0; c < 3; ++c)
+            dir[edge_key((uint32_t)s.tri[3 * t + c], (uint32_t)s.tri[3 * t + (c + 1) % 3])] =
+                (int32_t)t;
+    auto across = [&](int32_t cur, int32_t a, int32_t b) -> int32_t {
+        auto it = dir.find(edge_key((uint32_t)a, (uint32_t)b));
+        int32_t t1 = it == dir.end() ? -1 : it->second;
+        if (t1 != cur) return t1;
+        auto it2 = dir.find(edge_key((uint32_t)b, (uint32_t)a));
+        return it2 == dir.end() ? -1 : it2->second;
+    };
+    auto third = [&](int32_t t, int32_t a, int32_t b) -> int32_t {
+        for (int c = 0; c < 3; ++c) {
+            const int32_t v = s.tri[3 * t + c];
+            if (v != a && v != b) return v;
+        }
+        return -1;
+    };
+    std::vector<uint8_t> used((size_t)nt, 0);
+    std::vector<int32_t> stamp((size_t)nt, -1);
+    std::vector<Strip> out;
+    int32_t attempt = 0;
+    for (int64_t seed = 0; seed < nt; ++seed) {
+        if (used[seed]) continue;
+        int best_rot = 0;
+        int64_t best_len = -1;
+        for (int rot = 0; rot < 3; ++rot) {
+            ++attempt;
+            int32_t y = s.tri[3 * seed + (rot + 1) % 3], z = s.tri[3 * seed + (rot + 2) % 3];
+            int32_t cur = (int32_t)seed;
+            stamp[cur] = attempt;
+            int64_t len = 1;
+            for (;;) {
+                const int32_t nb = across(cur, y, z);
+                if (nb < 0 || used[nb] || stamp[nb] == attempt) break;
+                stamp[nb] = attempt;
+                const int32_t w = third(nb, y, z);
+                y = z;
+                z = w;
+                cur = nb;
+                ++len;
+            }
+            if (len > best_len) { best_len = len; best_rot = rot; }
+        }
+        Strip st;
+        const int32_t x0 = s.tri[3 * seed + best_rot], y0 = s.tri[3 * seed + (best_rot + 1) % 3],
+                      z0 = s.tri[3 * seed + (best_rot + 2) % 3];
+        st.verts = {x0, y0, z0};
+        st.tris = {(int32_t)seed};
+        used[seed] = 1;
+        int32_t y = y0, z = z0, cur = (int32_t)seed;
+        for (;;) {
+            const int32_t nb = across(cur, y, z);
+            if (nb < 0 || used[nb]) break;
+            used[nb] = 1;
+            const int32_t w = third(nb, y, z);
+            st.verts.push_back(w);
+            st.tris.push_back(nb);
+            y = z;
+            z = w;
+            cur = nb;
+        }
+        out.push_back(std::move(st));
+    }
+    return out;
+}
+
+// +1 when (p, q, r) is a rotation of the triangle's stored order, else -1.
+double parity(const int32_t *f, int32_t p, int32_t q, int32_t r) {
+    for (int c = 0; c < 3; ++c)
+        if (f[c] == p && f[(c + 1) % 3] == q && f[(c + 2) % 3] == r) return 1.0;
+    return -1.0;
+}
+
+}  // namespace
+
+sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int32_t n,
+                             uint32_t flags, sal_surface_set **out) {
+    if (!ctx || !desc || !out) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+    if (n < 1 || n > kMaxSurfaces)
+        return set_error(SAL_ERR_INVALID_ARG, "n_surfaces must be in 1..64");
+    std::vector<Rec32> r32;
+    std::vector<Rec64> r64;
+    std::vector<int64_t> strip_off;
+    std::vector<SurfaceDev> table((size_t)n);
+    int64_t total_tri = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        HostSurface hs;
+        hs.xyz = desc[i].xyz;
+        hs.nv = desc[i].n_vertices;
+        hs.nt = desc[i].n_triangles;
+        hs.label = desc[i].label;
+        if (hs.nt < 4 || !desc[i].tri || !desc[i].xyz)
+            return set_error(SAL_ERR_INVALID_ARG,
+                             "surface " + std::to_string(i) + ": needs >= 4 triangles");
+        hs.tri.assign(desc[i].tri, desc[i].tri + 3 * hs.nt);
+        sal_status st = validate(hs, i, (flags & SAL_SURF_AUTO_ORIENT) != 0);
+        if (st != SAL_OK) return st;
+        const std::vector<Strip> strips = make_strips(hs);
+        SurfaceDev &sd = table[(size_t)i];
+        sd.rec_begin = (int64_t)r32.size();
+        sd.strip_begin = (int64_t)strip_off.size();
+        sd.n_tri = hs.nt;
+        sd.label = hs.label;
+        sd.pad = 0;
+        total_tri += hs.nt;
+        const float *V = hs.xyz;
+        for (const Strip &s : strips) {
+            strip_off.push_back((int64_t)r32.size());
+            const int m = (int)s.tris.size();
+            Rec32 h32{};
+            Rec64 h64{};
+            for (int c = 0; c < 3; ++c) {
+                h32.v[c] = V[3 * s.verts[0] + c];
+                h32.v[3 + c] = V[3 * s.verts[1] + c];
+                h64.v[c] = V[3 * s.verts[0] + c];
+                h64.v[3 + c] = V[3 * s.verts[1] + c];
+            }
+            int32_t mi = m;
+            std::memcpy(&h32.v[6], &mi, 4);
+            int64_t ml = m;
+            std::memcpy(&h64.v[6], &ml, 8);
+            r32.push_back(h32);
+            r64.push_back(h64);
+            for (int t = 0; t < m; ++t) {
+                const int32_t *f = &hs.tri[3 * (size_t)s.tris[t]];
+                const float *A = V + 3 * f[0], *B = V + 3 * f[1], *C = V + 3 * f[2];
+                const double e1[3] = {(double)B[0] - A[0], (double)B[1] - A[1], (double)B[2] - A[2]};
+                const double e2[3] = {(double)C[0] - A[0], (double)C[1] - A[1], (double)C[2] - A[2]};
+                const double nn[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                      e1[0] * e2[1] - e1[1] * e2[0]};
+                const double nlen = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+                const double nb = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]) *
+                                  std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+                const int32_t z = s.verts[t + 2];
+                Rec32 q32{};
+                Rec64 q64{};
+                for (int c = 0; c < 3; ++c) {
+                    q32.v[c] = V[3 * z + c];
+                    q32.v[3 + c] = (float)(kNScale * nn[c]);
+                    q64.v[c] = V[3 * z + c];
+                    q64.v[3 + c] = nn[c];
+                }
+                q32.v[6] = (float)nlen;
+                q32.v[7] = (float)(kKnSmall * nlen);
+                q64.v[6] = nb * (1.0 + 1e-12);
+                q64.v[7] = parity(f, s.verts[t], s.verts[t + 1], s.verts[t + 2]);
+                r32.push_back(q32);
+                r64.push_back(q64);
+            }
+        }
+        sd.rec_end = (int64_t)r32.size();
+        sd.strip_end = (int64_t)strip_off.size();
+    }
+
+    SAL_HIP(hipSetDevice(ctx->device));
+    auto *set = new sal_surface_set();
+    set->device = ctx->device;
+    set->n_surf = n;
+    set->n_tri = total_tri;
+    set->n_strips = (int64_t)strip_off.size();
+    set->n_rec = (int64_t)r32.size();
+    set->host_table = table;
+    sal_status st = SAL_OK;
+    auto up = [&](void **dst, const void *src, size_t bytes) -> sal_status {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return hip_error(e, "hipMalloc(surface set)");
+        e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_error(e, "hipMemcpy(surface set)");
+        set->bytes += bytes;
+        return SAL_OK;
+    };
+    if ((st = up((void **)&set->rec32, r32.data(), r32.size() * sizeof(Rec32))) != SAL_OK ||
+        (st = up((void **)&set->rec64, r64.data(), r64.size() * sizeof(Rec64))) != SAL_OK ||
+        (st = up((void **)&set->surf, table.data(), table.size() * sizeof(SurfaceDev))) != SAL_OK ||
+        (st = up((void **)&set->strip_off, strip_off.data(), strip_off.size() * sizeof(int64_t))) !=
+            SAL_OK) {
+        destroy_surface_set(set);
+        return st;
+    }
+    *out = set;
+    return SAL_OK;
+}
+
+void destroy_surface_set(sal_surface_set *set) {
+    if (!set) return;
+    (void)hipSetDevice(set->device);
+    if (set->rec32) (void)hipFree(set->rec32);
+    if (set->rec64) (void)hipFree(set->rec64);
+    if (set->surf) (void)hipFree(set->surf);
+    if (set->strip_off) (void)hipFree(set->strip_off);
+    delete set;
+}
+
+}  // namespace sal

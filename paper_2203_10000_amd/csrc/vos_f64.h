@@ -1,0 +1,98 @@
+// Van Oosterom-Strackee solid angle in double precision along a triangle
+// strip (the FP64 form and the FP64 recheck).
+//
+// For a point p and triangle (A, B, C) with a = A - p, b = B - p, c = C - p:
+//   Omega / 2 = atan2(N, D),  N = a . (b x c),
+//   D = |a||b||c| + (a.b)|c| + (a.c)|b| + (b.c)|a|
+// (Van Oosterom & Strackee, IEEE Trans. Biomed. Eng. 30(2), 1983; the
+// paper's section 2.1.3 labels a point by the solid angle of a closed surface
+// over 4 pi).  D is symmetric in (a, b, c), so the strip order of the three
+// vertices only matters for the sign of N, which is taken from the outward
+// normal n = (B - A) x (C - A) stored per triangle: N = (Z - p) . n for any
+// vertex Z of the triangle.
+//
+// When |N| is below its rounding-error bound the sign comes from the exact
+// predicate; a point exactly on the triangle's plane and inside the closed
+// triangle is "on the surface" (enclosed), otherwise it contributes 0.
+#pragma once
+
+#include "exact_dev.h"
+#include "sal_internal.h"
+
+namespace sal {
+
+struct StripF64 {
+    double dx0, dy0, dz0, r0;   // older vertex X: X - p, |X - p|
+    double dx1, dy1, dz1, r1;   // newer vertex Y
+    double e01, rr01;           // (X - p).(Y - p), |X - p||Y - p|
+    float X[3], Y[3];           // raw coordinates (exact predicate inputs)
+};
+
+__device__ __forceinline__ void f64_strip_head(StripF64 &s, const double *h, const double *p) {
+    s.dx0 = h[0] - p[0];
+    s.dy0 = h[1] - p[1];
+    s.dz0 = h[2] - p[2];
+    s.dx1 = h[3] - p[0];
+    s.dy1 = h[4] - p[1];
+    s.dz1 = h[5] - p[2];
+    s.r0 = sqrt(s.dx0 * s.dx0 + s.dy0 * s.dy0 + s.dz0 * s.dz0);
+    s.r1 = sqrt(s.dx1 * s.dx1 + s.dy1 * s.dy1 + s.dz1 * s.dz1);
+    s.e01 = s.dx0 * s.dx1 + s.dy0 * s.dy1 + s.dz0 * s.dz1;
+    s.rr01 = s.r0 * s.r1;
+    s.X[0] = (float)h[0];
+    s.X[1] = (float)h[1];
+    s.X[2] = (float)h[2];
+    s.Y[0] = (float)h[3];
+    s.Y[1] = (float)h[4];
+    s.Y[2] = (float)h[5];
+}
+
+// Out-of-line exact resolution of a triangle whose N sign is uncertain.
+// Returns the corrected N (exact sign, magnitude kept) or 0 with *coplanar set.
+__device__ __noinline__ double f64_exact_n(const float *praw, const float *X, const float *Y,
+                                           const float *Z, double sigma, double n_val,
+                                           int *on, bool *coplanar) {
+    const int o = exact_orient3d(praw, X, Y, Z) * (sigma > 0.0 ? 1 : -1);
+    if (o == 0) {
+        *coplanar = true;
+        if (exact_in_triangle(praw, X, Y, Z)) *on = 1;
+        return 0.0;
+    }
+    *coplanar = false;
+    const double mag = n_val != 0.0 ? fabs(n_val) : 2.2250738585072014e-308;
+    return o > 0 ? mag : -mag;
+}
+
+// One strip step: the triangle (X, Y, Z) with Z and its normal in record t.
+// Returns atan2(N, D) (half the solid angle); advances the strip window.
+__device__ __forceinline__ double f64_strip_tri(StripF64 &s, const double *t, const double *p,
+                                                const float *praw, int *on,
+                                                unsigned *n_exact) {
+    const double dx2 = t[0] - p[0], dy2 = t[1] - p[1], dz2 = t[2] - p[2];
+    const double r2 = sqrt(dx2 * dx2 + dy2 * dy2 + dz2 * dz2);
+    const double e02 = s.dx0 * dx2 + s.dy0 * dy2 + s.dz0 * dz2;
+    const double e12 = s.dx1 * dx2 + s.dy1 * dy2 + s.dz1 * dz2;
+    double num = dx2 * t[3] + dy2 * t[4] + dz2 * t[5];
+    const double den = s.rr01 * r2 + s.e01 * r2 + e02 * s.r1 + e12 * s.r0;
+    double half = 0.0;
+    // |N - N_exact| <= ~10 eps |Z - p| |B - A| |C - A|; 32 eps leaves margin.
+    if (fabs(num) <= 32.0 * 1.1102230246251565e-16 * r2 * t[6]) {
+        const float Z[3] = {(float)t[0], (float)t[1], (float)t[2]};
+        bool coplanar = false;
+        num = f64_exact_n(praw, s.X, s.Y, Z, t[7], num, on, &coplanar);
+        *n_exact += 1;
+        if (!coplanar) half = atan2(num, den);
+    } else {
+        half = atan2(num, den);
+    }
+    // slide the window: (X, Y) <- (Y, Z)
+    s.dx0 = s.dx1; s.dy0 = s.dy1; s.dz0 = s.dz1; s.r0 = s.r1;
+    s.dx1 = dx2; s.dy1 = dy2; s.dz1 = dz2; s.r1 = r2;
+    s.e01 = e12;
+    s.rr01 = s.r0 * r2;
+    s.X[0] = s.Y[0]; s.X[1] = s.Y[1]; s.X[2] = s.Y[2];
+    s.Y[0] = (float)t[0]; s.Y[1] = (float)t[1]; s.Y[2] = (float)t[2];
+    return half;
+}
+
+}  // namespace sal
