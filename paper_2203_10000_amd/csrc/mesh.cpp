@@ -1,0 +1,389 @@
+// Tetrahedral mesh: Kuhn lattice creation, recursive refine-and-relabel
+// rounds (paper section 2.1.3 item 2), export of the leaves.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "mesh_internal.h"
+#include "runtime.h"
+
+namespace sal {
+
+// Children tables from the parent rule: the level-(l+1) tetrahedron (code,
+// q') in sub-cell `code` lies in the parent q when sorting U_a = 4 d_a + w_a
+// (w = 3, 2, 1 along q''s permutation) in decreasing order gives q's
+// permutation.
+static ChildTables make_child_tables() {
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    ChildTables T;
+    std::memset(&T, -1, sizeof(T));
+    int count[6] = {0, 0, 0, 0, 0, 0};
+    for (int code = 0; code < 8; ++code) {
+        for (int cq = 0; cq < 6; ++cq) {
+            int w[3], U[3];
+            w[perm[cq][0]] = 3;
+            w[perm[cq][1]] = 2;
+            w[perm[cq][2]] = 1;
+            for (int a = 0; a < 3; ++a) U[a] = 4 * ((code >> a) & 1) + w[a];
+            int pq = -1;
+            for (int q = 0; q < 6; ++q)
+                if (U[perm[q][0]] > U[perm[q][1]] && U[perm[q][1]] > U[perm[q][2]]) pq = q;
+            const int r = count[pq]++;
+            T.list[pq][r][0] = (int8_t)code;
+            T.list[pq][r][1] = (int8_t)cq;
+            T.rank[pq][code][cq] = (int8_t)r;
+        }
+    }
+    return T;
+}
+
+}  // namespace sal
+
+struct sal_tet_mesh {
+    int device = 0;
+    sal::LatticeGeom g{};
+    sal::ChildTables T{};
+    int64_t n[sal::kMaxLevels + 1] = {};
+    int64_t cap[sal::kMaxLevels + 1] = {};
+    uint64_t *key[sal::kMaxLevels + 1] = {};
+    int32_t *label[sal::kMaxLevels + 1] = {};
+    int32_t *child[sal::kMaxLevels + 1] = {};
+    uint8_t *flag[sal::kMaxLevels + 1] = {};
+    int max_level = 0;
+    bool labeled0 = false;
+    int64_t n_leaves = 0;
+    // scratch
+    float *cen[3] = {};
+    int64_t cen_cap = 0;
+    int32_t *list = nullptr;
+    int64_t list_cap = 0;
+    int64_t *blocks = nullptr;
+    int64_t blocks_cap = 0;
+    int64_t *totals = nullptr;   // kMaxLevels + 1 counts
+    hipEvent_t ev[16] = {};
+};
+
+namespace sal {
+namespace {
+
+sal::LevelPtrs ptrs(const sal_tet_mesh *m) {
+    LevelPtrs L;
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        L.key[l] = m->key[l];
+        L.label[l] = m->label[l];
+        L.child[l] = m->child[l];
+        L.flag[l] = m->flag[l];
+        L.n[l] = m->n[l];
+    }
+    return L;
+}
+
+template <typename T>
+sal_status grow(T **p, int64_t old_n, int64_t new_cap, hipStream_t s) {
+    T *q = nullptr;
+    SAL_HIP(hipMalloc((void **)&q, (size_t)new_cap * sizeof(T)));
+    if (*p && old_n > 0)
+        SAL_HIP(hipMemcpyAsync(q, *p, (size_t)old_n * sizeof(T), hipMemcpyDeviceToDevice, s));
+    if (*p) {
+        SAL_HIP(hipStreamSynchronize(s));
+        SAL_HIP(hipFree(*p));
+    }
+    *p = q;
+    return SAL_OK;
+}
+
+sal_status ensure_level(sal_tet_mesh *m, int l, int64_t need, hipStream_t s) {
+    if (need <= m->cap[l]) return SAL_OK;
+    int64_t cap = m->cap[l] + m->cap[l] / 2;
+    if (cap < need) cap = need;
+    sal_status st;
+    if (l > 0 && (st = grow(&m->key[l], m->n[l], cap, s)) != SAL_OK) return st;
+    if ((st = grow(&m->label[l], m->n[l], cap, s)) != SAL_OK) return st;
+    if ((st = grow(&m->child[l], m->n[l], cap, s)) != SAL_OK) return st;
+    if ((st = grow(&m->flag[l], 0, cap, s)) != SAL_OK) return st;
+    m->cap[l] = cap;
+    return SAL_OK;
+}
+
+template <typename T>
+sal_status ensure_buf(T **p, int64_t *cap, int64_t need, hipStream_t s) {
+    if (need <= *cap) return SAL_OK;
+    const int64_t c = need + need / 4 + 1024;
+    sal_status st = grow(p, 0, c, s);
+    if (st == SAL_OK) *cap = c;
+    return st;
+}
+
+sal_status ensure_centroids(sal_tet_mesh *m, int64_t need, hipStream_t s) {
+    if (need <= m->cen_cap) return SAL_OK;
+    const int64_t c = need + need / 4 + 1024;
+    for (int a = 0; a < 3; ++a) {
+        int64_t dummy = 0;
+        sal_status st = grow(&m->cen[a], 0, c, s);
+        (void)dummy;
+        if (st != SAL_OK) return st;
+    }
+    m->cen_cap = c;
+    return SAL_OK;
+}
+
+sal_status compact(sal_tet_mesh *m, const CompactSrc &src, int64_t n, int32_t *out, int64_t *total,
+                   hipStream_t s) {
+    sal_status st = ensure_buf(&m->blocks, &m->blocks_cap, compact_blocks(n) + 1, s);
+    if (st != SAL_OK) return st;
+    SAL_HIP(launch_compact(src, n, m->blocks, total, out, s));
+    return SAL_OK;
+}
+
+// Labels n points whose centroids sit in the scratch into `labels`.
+sal_status label_scratch(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set, int64_t n,
+                         const sal_label_options &opt, int32_t *labels) {
+    if (n <= 0) return SAL_OK;
+    if (opt.precision == SAL_PREC_FP32_RECHECK) {
+        sal_status st = ensure_flag_capacity(ctx, n);
+        if (st != SAL_OK) return st;
+    }
+    SAL_HIP(launch_fill_u64(ctx->counters + kCntFlagged, 0ull, 1, ctx->stream));
+    return enqueue_label(ctx, set, n, m->cen[0], m->cen[1], m->cen[2], opt, labels, nullptr,
+                         nullptr);
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0f;
+    return ms;
+}
+
+}  // namespace
+}  // namespace sal
+
+using namespace sal;
+
+extern "C" {
+
+void sal_tet_mesh_destroy(sal_tet_mesh *m) {
+    if (!m) return;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        if (m->key[l]) (void)hipFree(m->key[l]);
+        if (m->label[l]) (void)hipFree(m->label[l]);
+        if (m->child[l]) (void)hipFree(m->child[l]);
+        if (m->flag[l]) (void)hipFree(m->flag[l]);
+    }
+    for (auto &c : m->cen)
+        if (c) (void)hipFree(c);
+    if (m->list) (void)hipFree(m->list);
+    if (m->blocks) (void)hipFree(m->blocks);
+    if (m->totals) (void)hipFree(m->totals);
+    for (auto &e : m->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete m;
+}
+
+sal_status sal_tet_mesh_create_lattice(sal_context *ctx, const double origin[3], double h,
+                                       const int32_t cells[3], sal_tet_mesh **out) {
+    try {
+        if (out) *out = nullptr;
+        if (!ctx || !origin || !cells || !out) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+        if (!(std::isfinite(h) && h > 0.0)) return set_error(SAL_ERR_INVALID_ARG, "h must be > 0");
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(origin[a])) return set_error(SAL_ERR_INVALID_ARG, "non-finite origin");
+            if (cells[a] < 1 || cells[a] > (1 << 16))
+                return set_error(SAL_ERR_INVALID_ARG, "cells must be in 1..65536 per axis");
+        }
+        const int64_t n0 = 6ll * cells[0] * cells[1] * cells[2];
+        if (n0 > 0x7fffffffll)
+            return set_error(SAL_ERR_CAPACITY, "more than 2^31 lattice tetrahedra");
+        SAL_HIP(hipSetDevice(ctx->device));
+        auto *m = new sal_tet_mesh();
+        m->device = ctx->device;
+        for (int a = 0; a < 3; ++a) {
+            m->g.origin[a] = origin[a];
+            m->g.cells[a] = cells[a];
+        }
+        m->g.h = h;
+        m->T = make_child_tables();
+        sal_status st = SAL_OK;
+        auto fail = [&](sal_status s) { sal_tet_mesh_destroy(m); return s; };
+        for (auto &e : m->ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(set_error(SAL_ERR_DEVICE, "hipEventCreate"));
+        if ((st = ensure_level(m, 0, n0, ctx->stream)) != SAL_OK) return fail(st);
+        m->n[0] = n0;
+        if (hipMalloc((void **)&m->totals, (kMaxLevels + 1) * sizeof(int64_t)) != hipSuccess)
+            return fail(set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(totals)"));
+        if (hipError_t e = launch_fill_i32(m->child[0], -1, n0, ctx->stream); e != hipSuccess)
+            return fail(hip_error(e, "fill child"));
+        if (hipError_t e = launch_fill_i32(m->label[0], -2, n0, ctx->stream); e != hipSuccess)
+            return fail(hip_error(e, "fill label"));
+        m->n_leaves = n0;
+        *out = m;
+        return SAL_OK;
+    } catch (...) {
+        return set_error(SAL_ERR_INTERNAL, "exception in sal_tet_mesh_create_lattice");
+    }
+}
+
+sal_status sal_tet_mesh_size(const sal_tet_mesh *m, int64_t *n_leaves, int32_t *max_level) {
+    if (!m) return set_error(SAL_ERR_INVALID_ARG, "mesh is NULL");
+    if (n_leaves) *n_leaves = m->n_leaves;
+    if (max_level) *max_level = m->max_level;
+    return SAL_OK;
+}
+
+sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
+                              int32_t rounds, const sal_label_options *opt_in,
+                              sal_refine_stats *per_round) {
+    try {
+        if (!ctx || !m || !set) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+        if (rounds < 0) return set_error(SAL_ERR_INVALID_ARG, "rounds < 0");
+        if (set->device != ctx->device || m->device != ctx->device)
+            return set_error(SAL_ERR_INVALID_ARG, "objects live on different devices");
+        sal_label_options opt;
+        sal_status st = resolve_options(opt_in, &opt);
+        if (st != SAL_OK) return st;
+        opt.winding_type = SAL_WINDING_NONE;
+        if (m->max_level + rounds > kMaxLevels)
+            return set_error(SAL_ERR_CAPACITY, "at most 3 refinement levels");
+        SAL_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = ctx->stream;
+        if (per_round) std::memset(per_round, 0, sizeof(sal_refine_stats) * (size_t)(rounds + 1));
+        unsigned long long cnt[kNumCounters];
+
+        // round 0: the whole lattice (paper section 2.1.3 item 1)
+        SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, s));
+        SAL_HIP(hipEventRecord(m->ev[0], s));
+        int64_t labeled0 = 0;
+        if (!m->labeled0) {
+            if ((st = ensure_centroids(m, m->n[0], s)) != SAL_OK) return st;
+            SAL_HIP(launch_lattice_centroids(m->g, m->n[0], m->cen[0], m->cen[1], m->cen[2], s));
+            if ((st = label_scratch(ctx, m, set, m->n[0], opt, m->label[0])) != SAL_OK) return st;
+            m->labeled0 = true;
+            labeled0 = m->n[0];
+        }
+        SAL_HIP(hipEventRecord(m->ev[1], s));
+        if (per_round) {
+            SAL_HIP(hipEventSynchronize(m->ev[1]));
+            SAL_HIP(hipMemcpy(cnt, ctx->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+            sal_refine_stats &r0 = per_round[0];
+            r0.n_leaves = m->n_leaves;
+            r0.n_labeled = labeled0;
+            r0.n_pairs = labeled0 * set->n_tri;
+            r0.n_recheck_pairs = (int64_t)cnt[kCntRecheck];
+            r0.ms_label = elapsed(m->ev[0], m->ev[1]);
+            r0.ms_total = r0.ms_label;
+        }
+
+        for (int r = 1; r <= rounds; ++r) {
+            const int top = m->max_level;
+            int64_t total_entries = 0;
+            for (int l = 0; l <= top; ++l) total_entries += m->n[l];
+            if ((st = ensure_buf(&m->list, &m->list_cap, total_entries, s)) != SAL_OK) return st;
+            SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, s));
+            SAL_HIP(hipEventRecord(m->ev[2], s));
+            for (int l = 0; l <= top; ++l) SAL_HIP(launch_fill_u8(m->flag[l], 0, m->n[l], s));
+            LevelPtrs L = ptrs(m);
+            for (int l = 0; l <= top; ++l) SAL_HIP(launch_mark(L, m->g, m->T, l, s));
+            SAL_HIP(hipEventRecord(m->ev[3], s));
+            int64_t off[kMaxLevels + 2] = {0};
+            for (int l = 0; l <= top; ++l) {
+                off[l + 1] = off[l] + m->n[l];
+                CompactSrc src{m->flag[l], nullptr};
+                if ((st = compact(m, src, m->n[l], m->list + off[l], m->totals + l, s)) != SAL_OK)
+                    return st;
+            }
+            SAL_HIP(hipEventRecord(m->ev[4], s));
+            int64_t count[kMaxLevels + 1] = {0};
+            SAL_HIP(hipMemcpyAsync(count, m->totals, sizeof(int64_t) * (top + 1),
+                                   hipMemcpyDeviceToHost, s));
+            SAL_HIP(hipStreamSynchronize(s));
+            if (top == kMaxLevels && count[top] > 0)
+                return set_error(SAL_ERR_CAPACITY, "refinement beyond level 3");
+            int64_t n_split = 0, n_label = 0;
+            float ms_split = 0.0f, ms_label = 0.0f;
+            // deepest level first: its children array never moves under a
+            // pending split of a coarser level
+            for (int l = top; l >= 0; --l) {
+                if (count[l] == 0) continue;
+                const int64_t kids = 8 * count[l];
+                if ((st = ensure_level(m, l + 1, m->n[l + 1] + kids, s)) != SAL_OK) return st;
+                if ((st = ensure_centroids(m, kids, s)) != SAL_OK) return st;
+                const int64_t base_block = m->n[l + 1] / 8;
+                LevelPtrs L2 = ptrs(m);
+                SAL_HIP(hipEventRecord(m->ev[5], s));
+                SAL_HIP(launch_split(L2, m->g, m->T, l, m->list + off[l], count[l], base_block,
+                                     m->cen[0], m->cen[1], m->cen[2], s));
+                SAL_HIP(hipEventRecord(m->ev[6], s));
+                m->n[l + 1] += kids;
+                if ((st = label_scratch(ctx, m, set, kids, opt, m->label[l + 1] + 8 * base_block)) !=
+                    SAL_OK)
+                    return st;
+                SAL_HIP(hipEventRecord(m->ev[7], s));
+                SAL_HIP(hipEventSynchronize(m->ev[7]));
+                ms_split += elapsed(m->ev[5], m->ev[6]);
+                ms_label += elapsed(m->ev[6], m->ev[7]);
+                if (l + 1 > m->max_level) m->max_level = l + 1;
+                n_split += count[l];
+                n_label += kids;
+            }
+            m->n_leaves += 7 * n_split;
+            SAL_HIP(hipEventRecord(m->ev[8], s));
+            if (per_round) {
+                SAL_HIP(hipEventSynchronize(m->ev[8]));
+                SAL_HIP(hipMemcpy(cnt, ctx->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+                sal_refine_stats &rs = per_round[r];
+                rs.n_leaves = m->n_leaves;
+                rs.n_boundary = n_split;
+                rs.n_labeled = n_label;
+                rs.n_pairs = n_label * set->n_tri;
+                rs.n_recheck_pairs = (int64_t)cnt[kCntRecheck];
+                rs.ms_mark = elapsed(m->ev[2], m->ev[3]);
+                rs.ms_compact = elapsed(m->ev[3], m->ev[4]);
+                rs.ms_split = ms_split;
+                rs.ms_label = ms_label;
+                rs.ms_total = elapsed(m->ev[2], m->ev[8]);
+            }
+        }
+        return SAL_OK;
+    } catch (...) {
+        return set_error(SAL_ERR_INTERNAL, "exception in sal_refine_relabel");
+    }
+}
+
+sal_status sal_tet_mesh_export(sal_context *ctx, const sal_tet_mesh *mc, uint64_t *keys,
+                               int32_t *labels, float *cx, float *cy, float *cz) {
+    try {
+        if (!ctx || !mc) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+        auto *m = const_cast<sal_tet_mesh *>(mc);
+        SAL_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = ctx->stream;
+        int64_t total_entries = 0;
+        for (int l = 0; l <= m->max_level; ++l) total_entries += m->n[l];
+        sal_status st = ensure_buf(&m->list, &m->list_cap, total_entries, s);
+        if (st != SAL_OK) return st;
+        int64_t off[kMaxLevels + 2] = {0};
+        for (int l = 0; l <= m->max_level; ++l) {
+            off[l + 1] = off[l] + m->n[l];
+            CompactSrc src{nullptr, m->child[l]};
+            if ((st = compact(m, src, m->n[l], m->list + off[l], m->totals + l, s)) != SAL_OK)
+                return st;
+        }
+        int64_t count[kMaxLevels + 1] = {0};
+        SAL_HIP(hipMemcpyAsync(count, m->totals, sizeof(int64_t) * (m->max_level + 1),
+                               hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipStreamSynchronize(s));
+        int64_t out_base = 0;
+        LevelPtrs L = ptrs(m);
+        for (int l = 0; l <= m->max_level; ++l) {
+            SAL_HIP(launch_export(L, m->g, l, m->list + off[l], count[l], out_base, keys, labels, cx,
+                                  cy, cz, s));
+            out_base += count[l];
+        }
+        if (out_base != m->n_leaves) return set_error(SAL_ERR_INTERNAL, "leaf count mismatch");
+        return SAL_OK;
+    } catch (...) {
+        return set_error(SAL_ERR_INTERNAL, "exception in sal_tet_mesh_export");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,367 @@
+// Kuhn lattice, label-boundary marking, compaction and 1 -> 8 split
+// (paper sections 2.1.1-2.1.3).  These passes are index arithmetic and
+// gathers, bound by memory traffic, not by arithmetic.
+//
+// Geometry in lattice units: a level-l tetrahedron is (cell c, permutation
+// pi = (p0, p1, p2) of the axes) = {1 >= f[p0] >= f[p1] >= f[p2] >= 0},
+// f = u 2^l - c; its vertices are x0 = c, x1 = x0 + e_p0, x2 = x1 + e_p1,
+// x3 = c + (1, 1, 1) (scaled by 2^-l).
+//
+// Same-level face neighbours (each shares the three other vertices):
+//   opposite x0: cell + e_p0, (p1, p2, p0)     opposite x1: cell, (p1, p0, p2)
+//   opposite x2: cell, (p0, p2, p1)            opposite x3: cell - e_p2, (p2, p0, p1)
+// Parent of a level-(l+1) tetrahedron (cell c', pi'): cell c' >> 1 and the
+// permutation sorting U_a = 4 (c'_a & 1) + w_a in decreasing order, where
+// w[pi'0] = 3, w[pi'1] = 2, w[pi'2] = 1 (U / 8 is the child's centroid in the
+// parent cell).
+#include <hip/hip_runtime.h>
+
+#include "mesh_internal.h"
+
+namespace sal {
+namespace {
+
+__device__ __forceinline__ void perm_of(int q, int &p0, int &p1, int &p2) {
+    // lexicographic permutations of (x, y, z)
+    p0 = q >> 1;
+    const int a = p0 == 0 ? 1 : 0;
+    const int b = p0 == 2 ? 1 : 2;
+    if (q & 1) { p1 = b; p2 = a; } else { p1 = a; p2 = b; }
+}
+
+__device__ __forceinline__ int q_of(int p0, int p1, int p2) { return 2 * p0 + (p1 > p2 ? 1 : 0); }
+
+__device__ __forceinline__ uint64_t make_key(int l, int q, int64_t i, int64_t j, int64_t k) {
+    return ((uint64_t)l << 60) | ((uint64_t)q << 57) | ((uint64_t)i << 38) | ((uint64_t)j << 19) |
+           (uint64_t)k;
+}
+
+__device__ __forceinline__ void split_key(uint64_t key, int &l, int &q, int64_t c[3]) {
+    l = (int)(key >> 60);
+    q = (int)((key >> 57) & 7u);
+    c[0] = (int64_t)((key >> 38) & 0x7ffffu);
+    c[1] = (int64_t)((key >> 19) & 0x7ffffu);
+    c[2] = (int64_t)(key & 0x7ffffu);
+}
+
+// Centroid in double, rounded once to float (no contraction: the value is
+// defined by the separately rounded product and sum).
+__device__ __forceinline__ void centroid(const LatticeGeom &g, int l, int q, const int64_t c[3],
+                                         float &x, float &y, float &z) {
+    int p0, p1, p2;
+    perm_of(q, p0, p1, p2);
+    double off[3];
+    off[p0] = 0.75;
+    off[p1] = 0.5;
+    off[p2] = 0.25;
+    const double hl = ldexp(g.h, -l);
+    x = (float)__dadd_rn(g.origin[0], __dmul_rn(hl, (double)c[0] + off[0]));
+    y = (float)__dadd_rn(g.origin[1], __dmul_rn(hl, (double)c[1] + off[1]));
+    z = (float)__dadd_rn(g.origin[2], __dmul_rn(hl, (double)c[2] + off[2]));
+}
+
+__global__ void k_lattice_centroids(LatticeGeom g, int64_t n0, float *__restrict__ cx,
+                                    float *__restrict__ cy, float *__restrict__ cz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n0) return;
+    const int q = (int)(i % 6);
+    int64_t cell = i / 6;
+    int64_t c[3];
+    c[0] = cell % g.cells[0];
+    cell /= g.cells[0];
+    c[1] = cell % g.cells[1];
+    c[2] = cell / g.cells[1];
+    centroid(g, 0, q, c, cx[i], cy[i], cz[i]);
+}
+
+__device__ __forceinline__ uint64_t entry_key(const LevelPtrs &L, const LatticeGeom &g, int l,
+                                              int64_t i) {
+    if (l > 0) return L.key[l][i];
+    const int q = (int)(i % 6);
+    int64_t cell = i / 6;
+    const int64_t cx = cell % g.cells[0];
+    cell /= g.cells[0];
+    const int64_t cy = cell % g.cells[1];
+    const int64_t cz = cell / g.cells[1];
+    return make_key(0, q, cx, cy, cz);
+}
+
+// The leaf containing the level-l tetrahedron (c, q): its (level, index), or
+// level -1 when (c, q) is itself refined (then its descendants are leaves).
+__device__ __forceinline__ void resolve(const LevelPtrs &L, const LatticeGeom &g,
+                                        const ChildTables &T, int l, int q, const int64_t c[3],
+                                        int &lv_out, int64_t &idx_out) {
+    int qa[kMaxLevels + 1];
+    int64_t ca[kMaxLevels + 1][3];
+    int rank[kMaxLevels + 1];
+    qa[l] = q;
+    ca[l][0] = c[0]; ca[l][1] = c[1]; ca[l][2] = c[2];
+    for (int lv = l; lv > 0; --lv) {
+        int p0, p1, p2;
+        perm_of(qa[lv], p0, p1, p2);
+        int w[3];
+        w[p0] = 3; w[p1] = 2; w[p2] = 1;
+        int U[3];
+        int dcode = 0;
+        for (int a = 0; a < 3; ++a) {
+            const int d = (int)(ca[lv][a] & 1);
+            U[a] = 4 * d + w[a];
+            dcode |= d << a;
+            ca[lv - 1][a] = ca[lv][a] >> 1;
+        }
+        // axes in decreasing U
+        int s0 = 0, s1 = 1, s2 = 2, tmp;
+        if (U[s1] > U[s0]) { tmp = s0; s0 = s1; s1 = tmp; }
+        if (U[s2] > U[s1]) { tmp = s1; s1 = s2; s2 = tmp; }
+        if (U[s1] > U[s0]) { tmp = s0; s0 = s1; s1 = tmp; }
+        qa[lv - 1] = q_of(s0, s1, s2);
+        rank[lv] = T.rank[qa[lv - 1]][dcode][qa[lv]];
+    }
+    int64_t idx = ((ca[0][2] * g.cells[1] + ca[0][1]) * g.cells[0] + ca[0][0]) * 6 + qa[0];
+    for (int lv = 0;; ++lv) {
+        const int32_t ch = L.child[lv][idx];
+        if (ch < 0) { lv_out = lv; idx_out = idx; return; }
+        if (lv == l) { lv_out = -1; idx_out = -1; return; }
+        idx = 8 * (int64_t)ch + rank[lv + 1];
+    }
+}
+
+// Section 2.1.3 (Fig. 3): a leaf is on a tissue boundary when a leaf sharing a
+// 2-D part of one of its faces carries another label.  Each leaf looks across
+// its four faces at the same level; when the other side is a leaf (or lies in
+// a coarser leaf) with another label, both are flagged.  When the other side
+// is finer, its leaves find this one the same way, so every pair is seen.
+__global__ void k_mark(LevelPtrs L, LatticeGeom g, ChildTables T, int l) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.n[l]) return;
+    if (L.child[l][i] >= 0) return;
+    const int32_t lab = L.label[l][i];
+    int q, lk;
+    int64_t c[3];
+    split_key(entry_key(L, g, l, i), lk, q, c);
+    int p0, p1, p2;
+    perm_of(q, p0, p1, p2);
+    const int64_t lim[3] = {(int64_t)g.cells[0] << l, (int64_t)g.cells[1] << l,
+                            (int64_t)g.cells[2] << l};
+    bool mine = false;
+    for (int f = 0; f < 4; ++f) {
+        int64_t nc[3] = {c[0], c[1], c[2]};
+        int nq;
+        if (f == 0) { nc[p0] += 1; nq = q_of(p1, p2, p0); }
+        else if (f == 1) { nq = q_of(p1, p0, p2); }
+        else if (f == 2) { nq = q_of(p0, p2, p1); }
+        else { nc[p2] -= 1; nq = q_of(p2, p0, p1); }
+        if (nc[0] < 0 || nc[1] < 0 || nc[2] < 0 || nc[0] >= lim[0] || nc[1] >= lim[1] ||
+            nc[2] >= lim[2])
+            continue;   // domain boundary
+        int lv;
+        int64_t j;
+        resolve(L, g, T, l, nq, nc, lv, j);
+        if (lv < 0) continue;
+        if (L.label[lv][j] != lab) {
+            mine = true;
+            L.flag[lv][j] = 1;
+        }
+    }
+    if (mine) L.flag[l][i] = 1;
+}
+
+// ------------------------------------------------------------- compaction
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ bool pred(const CompactSrc &s, int64_t i) {
+    return s.flag ? s.flag[i] != 0 : s.child[i] < 0;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_count(CompactSrc s, int64_t n,
+                                                        int64_t *__restrict__ block_counts) {
+    __shared__ int red[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int cnt = 0;
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+        if (i < n && pred(s, i)) ++cnt;
+    }
+    red[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = kScanThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_counts[blockIdx.x] = red[0];
+}
+
+// Exclusive scan of n_blocks counts in one workgroup; total -> *total.
+__global__ __launch_bounds__(1024) void k_scan_blocks(int64_t *__restrict__ counts, int64_t n_blocks,
+                                                     int64_t *__restrict__ total) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (n_blocks + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = b0 + per < n_blocks ? b0 + per : n_blocks;
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += counts[b];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;   // exclusive prefix of this thread's chunk
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t c = counts[b];
+        counts[b] = run;
+        run += c;
+    }
+    if (t == 1023) *total = part[1023];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scatter(CompactSrc s, int64_t n,
+                                                          const int64_t *__restrict__ offsets,
+                                                          int32_t *__restrict__ out) {
+    __shared__ int part[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int cnt = 0;
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t i = base + r;
+        if (i < n && pred(s, i)) ++cnt;
+    }
+    part[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t pos = offsets[blockIdx.x] + part[threadIdx.x] - cnt;
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t i = base + r;
+        if (i < n && pred(s, i)) out[pos++] = (int32_t)i;
+    }
+}
+
+// Section 2.1.2: each listed leaf of level l becomes 8 level-(l+1) tetrahedra
+// (red refinement); they are appended as one block, their centroids written
+// to the labeling scratch.
+__global__ void k_split(LevelPtrs L, LatticeGeom g, ChildTables T, int l,
+                        const int32_t *__restrict__ list, int64_t count, int64_t base_block,
+                        float *__restrict__ cx, float *__restrict__ cy, float *__restrict__ cz) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= count * 8) return;
+    const int64_t j = jj >> 3;
+    const int r = (int)(jj & 7);
+    const int64_t i = list[j];
+    int q, lk;
+    int64_t c[3];
+    split_key(entry_key(L, g, l, i), lk, q, c);
+    const int64_t b = base_block + j;
+    if (r == 0) L.child[l][i] = (int32_t)b;
+    const int dcode = T.list[q][r][0];
+    const int cq = T.list[q][r][1];
+    int64_t cc[3];
+    for (int a = 0; a < 3; ++a) cc[a] = 2 * c[a] + ((dcode >> a) & 1);
+    const int64_t o = 8 * b + r;
+    L.key[l + 1][o] = make_key(l + 1, cq, cc[0], cc[1], cc[2]);
+    L.child[l + 1][o] = -1;
+    L.label[l + 1][o] = -2;
+    centroid(g, l + 1, cq, cc, cx[jj], cy[jj], cz[jj]);
+}
+
+__global__ void k_export(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
+                         int64_t count, int64_t out_base, uint64_t *__restrict__ keys,
+                         int32_t *__restrict__ labels, float *__restrict__ cx,
+                         float *__restrict__ cy, float *__restrict__ cz) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const int64_t i = list[j];
+    const int64_t o = out_base + j;
+    const uint64_t key = entry_key(L, g, l, i);
+    if (keys) keys[o] = key;
+    if (labels) labels[o] = L.label[l][i];
+    if (cx || cy || cz) {
+        int q, lk;
+        int64_t c[3];
+        split_key(key, lk, q, c);
+        float x, y, z;
+        centroid(g, l, q, c, x, y, z);
+        if (cx) cx[o] = x;
+        if (cy) cy[o] = y;
+        if (cz) cz[o] = z;
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace
+
+hipError_t launch_lattice_centroids(const LatticeGeom &g, int64_t n0, float *cx, float *cy,
+                                    float *cz, hipStream_t s) {
+    if (n0 <= 0) return hipSuccess;
+    k_lattice_centroids<<<grid_for(n0, 256), 256, 0, s>>>(g, n0, cx, cy, cz);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark(const LevelPtrs &L, const LatticeGeom &g, const ChildTables &T, int l,
+                       hipStream_t s) {
+    if (L.n[l] <= 0) return hipSuccess;
+    k_mark<<<grid_for(L.n[l], 256), 256, 0, s>>>(L, g, T, l);
+    return hipGetLastError();
+}
+
+int64_t compact_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_compact(const CompactSrc &src, int64_t n, int64_t *block_scratch,
+                          int64_t *total, int32_t *out, hipStream_t s) {
+    const int64_t nb = compact_blocks(n);
+    if (nb <= 0) return launch_fill_u64((unsigned long long *)total, 0ull, 1, s);
+    k_count<<<(unsigned)nb, kScanThreads, 0, s>>>(src, n, block_scratch);
+    k_scan_blocks<<<1, 1024, 0, s>>>(block_scratch, nb, total);
+    k_scatter<<<(unsigned)nb, kScanThreads, 0, s>>>(src, n, block_scratch, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_split(const LevelPtrs &L, const LatticeGeom &g, const ChildTables &T, int l,
+                        const int32_t *list, int64_t count, int64_t base_block, float *cx,
+                        float *cy, float *cz, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_split<<<grid_for(count * 8, 256), 256, 0, s>>>(L, g, T, l, list, count, base_block, cx, cy,
+                                                    cz);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
+                         int64_t count, int64_t out_base, uint64_t *keys, int32_t *labels,
+                         float *cx, float *cy, float *cz, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_export<<<grid_for(count, 256), 256, 0, s>>>(L, g, l, list, count, out_base, keys, labels,
+                                                  cx, cy, cz);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_u8<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace sal
