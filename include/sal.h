@@ -137,6 +137,9 @@ typedef struct sal_label_options {
     double kappa;             /* float32 conditioning threshold; 0 = 2^-5 */
     int32_t points_per_lane;  /* 0 = tuned; else 1, 2 or 4 */
     int32_t block_waves;      /* 0 = tuned; else 1, 2, 4 or 8 wavefronts per block */
+    int32_t use_graph;        /* sal_label_batch: 1 = capture the launch sequence in a
+                                 hipGraph and replay it while the same instances (same
+                                 surface sets, pointers, sizes, options) come back */
 } sal_label_options;
 
 /* Fills the defaults listed above. */

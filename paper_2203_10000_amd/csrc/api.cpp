@@ -25,6 +25,7 @@ sal_status ensure_flag_capacity(sal_context *ctx, int64_t n) {
     SAL_HIP(hipStreamSynchronize(ctx->stream));
     if (ctx->flag_list) SAL_HIP(hipFree(ctx->flag_list));
     ctx->flag_list = nullptr;
+    ctx->batch_graph_key = 0;   // a captured batch graph points at the old list
     ctx->flag_cap = 0;
     const int64_t cap = n < 4096 ? 4096 : n;
     SAL_HIP(hipMalloc((void **)&ctx->flag_list, (size_t)cap * sizeof(FlagEntry)));
@@ -46,7 +47,7 @@ sal_status resolve_options(const sal_label_options *in, sal_label_options *out) 
     if (out->kappa == 0.0) out->kappa = 0.03125;
     if (!(out->kappa > 0.0 && out->kappa < 1.0))
         return set_error(SAL_ERR_INVALID_ARG, "kappa must be in (0, 1)");
-    if (out->points_per_lane == 0) out->points_per_lane = 2;
+    if (out->points_per_lane == 0) out->points_per_lane = 1;
     if (out->points_per_lane != 1 && out->points_per_lane != 2 && out->points_per_lane != 4)
         return set_error(SAL_ERR_INVALID_ARG, "points_per_lane must be 0, 1, 2 or 4");
     if (out->block_waves == 0) out->block_waves = 4;
@@ -150,6 +151,7 @@ void sal_label_options_default(sal_label_options *o) {
     o->kappa = 0.0;
     o->points_per_lane = 0;
     o->block_waves = 0;
+    o->use_graph = 0;
 }
 
 sal_status sal_context_create(int device, void *stream, sal_context **out) {
@@ -174,6 +176,10 @@ sal_status sal_context_create(int device, void *stream, sal_context **out) {
     }
     e = hipMalloc((void **)&ctx->counters, kNumCounters * sizeof(unsigned long long));
     if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(counters)"); }
+    e = hipMalloc((void **)&ctx->batch_next, sizeof(unsigned int) * 4);
+    if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(batch counter)"); }
+    e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipStreamCreate"); }
     *out = ctx;
     return SAL_OK;
     SAL_GUARD_END
@@ -193,6 +199,14 @@ void sal_context_destroy(sal_context *ctx) {
         if (ev) (void)hipEventDestroy(ev);
     if (ctx->flag_list) (void)hipFree(ctx->flag_list);
     if (ctx->counters) (void)hipFree(ctx->counters);
+    if (ctx->batch_graph) (void)hipGraphExecDestroy(ctx->batch_graph);
+    if (ctx->batch_items) (void)hipFree(ctx->batch_items);
+    if (ctx->batch_insts) (void)hipFree(ctx->batch_insts);
+    if (ctx->batch_partial) (void)hipFree(ctx->batch_partial);
+    if (ctx->batch_mask) (void)hipFree(ctx->batch_mask);
+    if (ctx->batch_next) (void)hipFree(ctx->batch_next);
+    if (ctx->batch_counters) (void)hipFree(ctx->batch_counters);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
 }
 

@@ -1,0 +1,303 @@
+// sal_label_batch: work list construction, persistent launch, optional
+// hipGraph capture / replay.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "batch_internal.h"
+#include "runtime.h"
+
+namespace sal {
+namespace {
+
+template <typename T>
+sal_status ensure_dev(T **p, int64_t *have, int64_t need, hipStream_t s, sal_context *ctx) {
+    if (need <= *have) return SAL_OK;
+    SAL_HIP(hipStreamSynchronize(s));
+    if (*p) SAL_HIP(hipFree(*p));
+    *p = nullptr;
+    *have = 0;
+    const int64_t cap = need + need / 4 + 64;
+    SAL_HIP(hipMalloc((void **)p, (size_t)cap * sizeof(T)));
+    *have = cap;
+    ctx->batch_graph_key = 0;   // buffers moved: a captured graph is stale
+    return SAL_OK;
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+// Splits strips [b, e) of one surface into `parts` ranges of nearly equal
+// triangle counts; returns record boundaries.
+std::vector<int64_t> strip_ranges(const sal_surface_set *set, const SurfaceDev &sd, int parts) {
+    std::vector<int64_t> out;
+    out.push_back(sd.rec_begin);
+    if (parts > 1) {
+        const int64_t tot = sd.n_tri;
+        int64_t acc = 0;
+        int done = 1;
+        for (int64_t s = sd.strip_begin; s < sd.strip_end && done < parts; ++s) {
+            acc += set->host_strip_tris[(size_t)s];
+            if (acc * parts >= tot * done && s + 1 < sd.strip_end) {
+                out.push_back(set->host_strip_off[(size_t)s + 1]);
+                ++done;
+            }
+        }
+    }
+    out.push_back(sd.rec_end);
+    return out;
+}
+
+}  // namespace
+}  // namespace sal
+
+using namespace sal;
+
+extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst, int32_t n_inst,
+                                      const sal_label_options *opt_in, sal_label_stats *stats) {
+    try {
+        if (!ctx || (n_inst > 0 && !inst)) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+        if (n_inst < 0) return set_error(SAL_ERR_INVALID_ARG, "n_inst < 0");
+        sal_label_options opt;
+        sal_status st = resolve_options(opt_in, &opt);
+        if (st != SAL_OK) return st;
+        if (opt.winding_type != SAL_WINDING_NONE)
+            return set_error(SAL_ERR_INVALID_ARG, "the batched form has no winding output");
+        int64_t total = 0, total_pairs = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            const sal_instance &in = inst[i];
+            if (!in.surfaces) return set_error(SAL_ERR_INVALID_ARG, "instance without surfaces");
+            if (in.surfaces->device != ctx->device)
+                return set_error(SAL_ERR_INVALID_ARG, "instance surfaces on another device");
+            if (in.n_points < 0) return set_error(SAL_ERR_INVALID_ARG, "n_points < 0");
+            if (in.n_points > 0 && (!in.x || !in.y || !in.z || !in.labels))
+                return set_error(SAL_ERR_INVALID_ARG, "NULL point or label buffer");
+            total += in.n_points;
+            total_pairs += in.n_points * in.surfaces->n_tri;
+        }
+        if (stats) std::memset(stats, 0, sizeof(sal_label_stats) * (size_t)n_inst);
+        if (total == 0) return SAL_OK;
+        SAL_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = ctx->stream;
+
+        if (opt.precision == SAL_PREC_FP64) {
+            // the plain FP64 form has no float32 pass to batch: one launch per instance
+            for (int i = 0; i < n_inst; ++i) {
+                sal_label_stats one;
+                st = sal_label_points(ctx, inst[i].surfaces, inst[i].n_points, inst[i].x, inst[i].y,
+                                      inst[i].z, &opt, inst[i].labels, nullptr,
+                                      stats ? &one : nullptr);
+                if (st != SAL_OK) return st;
+                if (stats) stats[i] = one;
+            }
+            return SAL_OK;
+        }
+
+        // cache key of this batch (graph replay)
+        uint64_t key = 0x51ed270b2717ull;
+        for (int i = 0; i < n_inst; ++i) {
+            key = mix(key, inst[i].surfaces->uid);
+            key = mix(key, (uint64_t)inst[i].n_points);
+            key = mix(key, (uint64_t)(uintptr_t)inst[i].x);
+            key = mix(key, (uint64_t)(uintptr_t)inst[i].y);
+            key = mix(key, (uint64_t)(uintptr_t)inst[i].z);
+            key = mix(key, (uint64_t)(uintptr_t)inst[i].labels);
+        }
+        double kd = opt.kappa;
+        uint64_t kb;
+        std::memcpy(&kb, &kd, 8);
+        key = mix(key, kb);
+        std::memcpy(&kb, &opt.threshold, 8);
+        key = mix(key, kb);
+        std::memcpy(&kb, &opt.recheck_band, 8);
+        key = mix(key, kb);
+        key = mix(key, (uint64_t)n_inst);
+
+        st = ensure_flag_capacity(ctx, total);
+        if (st != SAL_OK) return st;
+        if ((st = ensure_dev(&ctx->batch_counters, &ctx->batch_counters_n,
+                             (int64_t)n_inst * kNumCounters, s, ctx)) != SAL_OK)
+            return st;
+
+        const bool replay = opt.use_graph && ctx->batch_graph && ctx->batch_graph_key == key;
+        BatchArgs a{};
+        if (!replay) {
+            // ---- work list: (instance, block, surface, strip range), largest first
+            const int64_t resident_waves = (int64_t)ctx->n_cu * 32;
+            int64_t cap = total_pairs / (8 * resident_waves);
+            if (cap < 64 * 4096) cap = 64 * 4096;
+            std::vector<BatchInst> hin((size_t)n_inst);
+            std::vector<BatchItem> items;
+            std::vector<int64_t> cost;
+            int64_t slot = 0, pbase = 0;
+            for (int i = 0; i < n_inst; ++i) {
+                const sal_surface_set *set = inst[i].surfaces;
+                BatchInst &b = hin[(size_t)i];
+                std::memset(&b, 0, sizeof(b));
+                b.rec32 = set->rec32;
+                b.rec64 = set->rec64;
+                b.surf = set->surf;
+                b.strip_off = set->strip_off;
+                b.x = inst[i].x;
+                b.y = inst[i].y;
+                b.z = inst[i].z;
+                b.labels = inst[i].labels;
+                b.n = inst[i].n_points;
+                b.point_base = pbase;
+                b.slot_base = slot;
+                b.n_surf = set->n_surf;
+                std::vector<std::vector<int64_t>> ranges((size_t)set->n_surf);
+                int32_t so = 0;
+                for (int k = 0; k < set->n_surf; ++k) {
+                    const SurfaceDev &sd = set->host_table[(size_t)k];
+                    int64_t parts = (64 * sd.n_tri + cap - 1) / cap;
+                    const int64_t ns = sd.strip_end - sd.strip_begin;
+                    if (parts > ns) parts = ns;
+                    if (parts < 1) parts = 1;
+                    ranges[(size_t)k] = strip_ranges(set, sd, (int)parts);
+                    b.split_off[k] = so;
+                    so += (int32_t)(ranges[(size_t)k].size() - 1);
+                    b.surf_label[k] = sd.label;
+                }
+                b.split_off[set->n_surf] = so;
+                b.splits_total = so;
+                const int64_t nb = (b.n + 63) / 64;
+                for (int64_t blk = 0; blk < nb; ++blk) {
+                    for (int k = 0; k < set->n_surf; ++k) {
+                        const auto &rg = ranges[(size_t)k];
+                        for (size_t r = 0; r + 1 < rg.size(); ++r) {
+                            BatchItem it;
+                            it.inst = i;
+                            it.surf = k;
+                            it.block = blk;
+                            it.rec_begin = rg[r];
+                            it.rec_end = rg[r + 1];
+                            it.slot = slot + blk * so + b.split_off[k] + (int64_t)r;
+                            items.push_back(it);
+                            cost.push_back(it.rec_end - it.rec_begin);
+                        }
+                    }
+                }
+                slot += nb * so;
+                pbase += b.n;
+            }
+            std::vector<int64_t> order(items.size());
+            std::iota(order.begin(), order.end(), 0);
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int64_t p, int64_t q) { return cost[(size_t)p] > cost[(size_t)q]; });
+            std::vector<BatchItem> sorted(items.size());
+            for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[(size_t)order[k]];
+
+            int64_t item_bytes_have = ctx->batch_items_bytes / (int64_t)sizeof(BatchItem);
+            if ((st = ensure_dev((BatchItem **)&ctx->batch_items, &item_bytes_have,
+                                 (int64_t)sorted.size(), s, ctx)) != SAL_OK)
+                return st;
+            ctx->batch_items_bytes = item_bytes_have * (int64_t)sizeof(BatchItem);
+            int64_t inst_have = ctx->batch_insts_bytes / (int64_t)sizeof(BatchInst);
+            if ((st = ensure_dev((BatchInst **)&ctx->batch_insts, &inst_have, (int64_t)n_inst, s,
+                                 ctx)) != SAL_OK)
+                return st;
+            ctx->batch_insts_bytes = inst_have * (int64_t)sizeof(BatchInst);
+            if (slot > ctx->batch_slots) {
+                SAL_HIP(hipStreamSynchronize(s));
+                if (ctx->batch_partial) SAL_HIP(hipFree(ctx->batch_partial));
+                if (ctx->batch_mask) SAL_HIP(hipFree(ctx->batch_mask));
+                ctx->batch_partial = nullptr;
+                ctx->batch_mask = nullptr;
+                ctx->batch_slots = 0;
+                ctx->batch_graph_key = 0;
+                const int64_t cap_slots = slot + slot / 4 + 64;
+                SAL_HIP(hipMalloc((void **)&ctx->batch_partial, (size_t)cap_slots * 64 * sizeof(double)));
+                SAL_HIP(hipMalloc((void **)&ctx->batch_mask, (size_t)cap_slots * sizeof(uint64_t)));
+                ctx->batch_slots = cap_slots;
+            }
+            // the previous call may still read these buffers
+            SAL_HIP(hipStreamSynchronize(s));
+            SAL_HIP(hipMemcpy(ctx->batch_items, sorted.data(), sorted.size() * sizeof(BatchItem),
+                              hipMemcpyHostToDevice));
+            SAL_HIP(hipMemcpy(ctx->batch_insts, hin.data(), hin.size() * sizeof(BatchInst),
+                              hipMemcpyHostToDevice));
+            a.n_items = (int64_t)sorted.size();
+        }
+        a.items = (const BatchItem *)ctx->batch_items;
+        a.insts = (const BatchInst *)ctx->batch_insts;
+        a.n_inst = n_inst;
+        a.total_points = total;
+        a.next_item = ctx->batch_next;
+        a.partial = ctx->batch_partial;
+        a.slot_mask = ctx->batch_mask;
+        a.kappa = (float)opt.kappa;
+        a.threshold = opt.threshold;
+        a.band = opt.recheck_band;
+        a.flag_list = ctx->flag_list;
+        a.counters = ctx->counters;
+        a.inst_counters = ctx->batch_counters;
+        const int pblocks = ctx->n_cu * 8;
+        const int rblocks = (int)std::min<int64_t>(total, (int64_t)ctx->n_cu * 8);
+
+        auto enqueue = [&](hipStream_t q) -> sal_status {
+            SAL_HIP(launch_fill_u64((unsigned long long *)ctx->batch_next, 0ull, 1, q));
+            SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, q));
+            SAL_HIP(launch_fill_u64(ctx->batch_counters, 0ull, (int64_t)n_inst * kNumCounters, q));
+            SAL_HIP(launch_batch(a, pblocks, rblocks, q));
+            return SAL_OK;
+        };
+
+        if (stats) SAL_HIP(hipEventRecord(ctx->ev[0], s));
+        if (opt.use_graph) {
+            if (!replay) {
+                if (ctx->batch_graph) {
+                    SAL_HIP(hipGraphExecDestroy(ctx->batch_graph));
+                    ctx->batch_graph = nullptr;
+                }
+                ctx->batch_graph_key = 0;
+                hipGraph_t g = nullptr;
+                SAL_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+                sal_status cst = enqueue(ctx->capture_stream);
+                hipError_t ee = hipStreamEndCapture(ctx->capture_stream, &g);
+                if (cst != SAL_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return cst;
+                }
+                if (ee != hipSuccess) return hip_error(ee, "hipStreamEndCapture");
+                ee = hipGraphInstantiate(&ctx->batch_graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ee != hipSuccess) return hip_error(ee, "hipGraphInstantiate");
+                ctx->batch_graph_key = key;
+                ctx->batch_graph_points = total;
+            }
+            SAL_HIP(hipGraphLaunch(ctx->batch_graph, s));
+        } else {
+            if ((st = enqueue(s)) != SAL_OK) return st;
+        }
+        if (stats) {
+            SAL_HIP(hipEventRecord(ctx->ev[2], s));
+            SAL_HIP(hipEventSynchronize(ctx->ev[2]));
+            float ms = 0.0f;
+            SAL_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]));
+            std::vector<unsigned long long> c((size_t)n_inst * kNumCounters);
+            SAL_HIP(hipMemcpy(c.data(), ctx->batch_counters, c.size() * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost));
+            for (int i = 0; i < n_inst; ++i) {
+                const unsigned long long *ci = c.data() + (size_t)i * kNumCounters;
+                stats[i].n_points = inst[i].n_points;
+                stats[i].n_pairs = inst[i].n_points * inst[i].surfaces->n_tri;
+                stats[i].n_recheck_points = (int64_t)ci[kCntFlagged];
+                stats[i].n_recheck_pairs = (int64_t)ci[kCntRecheck];
+                stats[i].n_band_flags = (int64_t)ci[kCntBand];
+                stats[i].n_cond_flags = (int64_t)ci[kCntCond];
+                stats[i].n_exact_fallbacks = (int64_t)ci[kCntExact];
+                stats[i].ms_total = ms;   // the whole batch (one launch sequence)
+                stats[i].ms_pairloop = ms;
+            }
+        }
+        return SAL_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(SAL_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return set_error(SAL_ERR_INTERNAL, "exception in sal_label_batch");
+    }
+}

@@ -11,134 +11,14 @@
 // cancellation near the surface), so it runs on the VALU, not on MFMA.
 #include <hip/hip_runtime.h>
 
+#include "pairloop_f32.h"
 #include "sal_internal.h"
 #include "vos_f64.h"
 
 namespace sal {
 namespace {
 
-constexpr double kInv2Pi = 0.15915494309189533577;
-constexpr float kPiF = 3.14159265358979323846f;
-
-// atan(t) for |t| <= 1/16 given t16 = 16 t:
-//   t16 (1/16 - t16^2 / (3 16^3) + t16^4 / (5 16^5)),
-// the Taylor series to t^5; the first omitted term is below 1e-8 t.
-constexpr float kA0 = 0.0625f;
-constexpr float kA1 = -8.1380208333e-05f;   // -1 / (3 * 4096)
-constexpr float kA2 = 1.9073486328e-07f;    //  1 / (5 * 1048576)
-
-__device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
-
-__device__ __forceinline__ int lane_id() {
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
-// Number of set bits of m below this lane.
-__device__ __forceinline__ int lanes_below(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ __forceinline__ int64_t bcast_i64(int64_t v, int src) {
-    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, src);
-    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), src);
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
-// Appends this lane's entry when `want` (wave-aggregated atomic).
-__device__ __forceinline__ void append_flag(const PairloopArgs &a, bool want, int64_t idx,
-                                            uint64_t enc, uint64_t flg) {
-    const uint64_t m = ballot(want);
-    if (m == 0) return;
-    const int leader = __builtin_ctzll(m);
-    int64_t base = 0;
-    if (lane_id() == leader)
-        base = (int64_t)atomicAdd(&a.counters[kCntFlagged], (unsigned long long)__popcll(m));
-    base = bcast_i64(base, leader);
-    if (want) {
-        FlagEntry e;
-        e.idx = idx;
-        e.enc = enc;
-        e.flg = flg;
-        a.flag_list[base + lanes_below(m)] = e;
-    }
-}
-
-__device__ __forceinline__ bool finite3(float x, float y, float z) {
-    return __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z);
-}
-
-// ------------------------------------------------------------------ float32
-// Records are read through the constant address space: the address is the
-// same for every lane, so each record is one scalar load into SGPRs.
-typedef __attribute__((address_space(4))) const Rec32 CRec32;
-typedef __attribute__((address_space(4))) const Rec64 CRec64;
-typedef __attribute__((address_space(4))) const SurfaceDev CSurf;
-
-struct Vtx {
-    float x, y, z, r;   // vertex - p and its length
-};
-
-// One strip step for P points: the triangle (O, N, Z) with Z and its normal in
-// record `rec`.  Z is written to the free slot F; the caller rotates the three
-// slots (O, N, F) -> (N, F, O) instead of moving registers.
-template <int P>
-__device__ __forceinline__ void f32_step(const Vtx (&O)[P], const Vtx (&N)[P], Vtx (&F)[P],
-                                         float (&e01)[P],
-                                         float (&rr01)[P], float (&acc)[P], const CRec32 *rec,
-                                         const float (&px)[P], const float (&py)[P],
-                                         const float (&pz)[P], const uint64_t (&good_mask)[P], float kap,
-                                         float branch_cut, uint64_t (&cmask)[P]) {
-    const float q0 = rec->v[0], q1 = rec->v[1], q2 = rec->v[2];
-    const float q3 = rec->v[3], q4 = rec->v[4], q5 = rec->v[5];
-    const float q6 = rec->v[6], q7 = rec->v[7];
-    float x2[P], y2[P], z2[P], r2[P], e02[P], e12[P], nn[P], mm[P], dd[P];
-    uint64_t near = 0;
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        x2[j] = q0 - px[j];
-        y2[j] = q1 - py[j];
-        z2[j] = q2 - pz[j];
-        r2[j] = __builtin_amdgcn_sqrtf(fmaf(x2[j], x2[j], fmaf(y2[j], y2[j], z2[j] * z2[j])));
-        e02[j] = fmaf(O[j].x, x2[j], fmaf(O[j].y, y2[j], O[j].z * z2[j]));
-        e12[j] = fmaf(N[j].x, x2[j], fmaf(N[j].y, y2[j], N[j].z * z2[j]));
-        nn[j] = fmaf(x2[j], q3, fmaf(y2[j], q4, z2[j] * q5));            // 16 N
-        mm[j] = rr01[j] * r2[j];                                         // |a||b||c|
-        dd[j] = fmaf(e12[j], O[j].r, fmaf(e02[j], N[j].r, fmaf(e01[j], r2[j], mm[j])));
-        // small-angle path: |N/D| < 1/16, D > kappa |a||b||c|, D > 5 |n| |c|
-        const float lim = fmaf(q7, r2[j], fmaf(kap, mm[j], fabsf(nn[j])));
-        near |= ballot(!(dd[j] > lim)) & good_mask[j];
-    }
-    if (near == 0) {
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const float t16 = nn[j] * __builtin_amdgcn_rcpf(dd[j]);
-            const float s = t16 * t16;
-            const float pl = fmaf(fmaf(kA2, s, kA1), s, kA0);
-            acc[j] = fmaf(t16, pl, acc[j]);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const float n1 = nn[j] * (1.0f / kNScale);
-            const float ang = atan2f(n1, dd[j]);
-            const float thr = fmaf(r2[j], kap * q6, kap * mm[j]);
-            const bool ill = fmaxf(fabsf(n1), fabsf(dd[j])) <= thr;
-            const bool cut = fabsf(ang) > branch_cut;
-            cmask[j] |= (ballot(ill) | ballot(cut)) & good_mask[j];
-            acc[j] += ang;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        rr01[j] = N[j].r * r2[j];
-        e01[j] = e12[j];
-        F[j].x = x2[j];
-        F[j].y = y2[j];
-        F[j].z = z2[j];
-        F[j].r = r2[j];
-    }
-}
+using namespace f32;
 
 template <int P>
 __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
@@ -177,39 +57,8 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
 #pragma unroll
         for (int j = 0; j < P; ++j) { S[j] = 0.0; cmask[j] = 0; }
 
-        for (int64_t r = surf[k].rec_begin; r < rec_end;) {
-            const CRec32 *h = rec + r;
-            const int m = __float_as_int(h->v[6]);
-            const float h0 = h->v[0], h1 = h->v[1], h2 = h->v[2];
-            const float h3 = h->v[3], h4 = h->v[4], h5 = h->v[5];
-            Vtx A[P], B[P], C[P];
-            float e01[P], rr01[P], acc[P];
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                A[j].x = h0 - px[j]; A[j].y = h1 - py[j]; A[j].z = h2 - pz[j];
-                B[j].x = h3 - px[j]; B[j].y = h4 - py[j]; B[j].z = h5 - pz[j];
-                A[j].r = __builtin_amdgcn_sqrtf(fmaf(A[j].x, A[j].x, fmaf(A[j].y, A[j].y, A[j].z * A[j].z)));
-                B[j].r = __builtin_amdgcn_sqrtf(fmaf(B[j].x, B[j].x, fmaf(B[j].y, B[j].y, B[j].z * B[j].z)));
-                e01[j] = fmaf(A[j].x, B[j].x, fmaf(A[j].y, B[j].y, A[j].z * B[j].z));
-                rr01[j] = A[j].r * B[j].r;
-                acc[j] = 0.0f;
-            }
-            const CRec32 *tr = h + 1;
-            int t = 0;
-            for (; t + 2 < m; t += 3) {
-                f32_step<P>(A, B, C, e01, rr01, acc, tr + t, px, py, pz, good_mask, kap, branch_cut, cmask);
-                f32_step<P>(B, C, A, e01, rr01, acc, tr + t + 1, px, py, pz, good_mask, kap, branch_cut, cmask);
-                f32_step<P>(C, A, B, e01, rr01, acc, tr + t + 2, px, py, pz, good_mask, kap, branch_cut, cmask);
-            }
-            if (t < m) {
-                f32_step<P>(A, B, C, e01, rr01, acc, tr + t, px, py, pz, good_mask, kap, branch_cut, cmask);
-                if (t + 1 < m)
-                    f32_step<P>(B, C, A, e01, rr01, acc, tr + t + 1, px, py, pz, good_mask, kap, branch_cut, cmask);
-            }
-#pragma unroll
-            for (int j = 0; j < P; ++j) S[j] += (double)acc[j];
-            r += m + 1;
-        }
+        surface_sum<P>(rec, surf[k].rec_begin, rec_end, px, py, pz, good_mask, kap, branch_cut, S,
+                       cmask);
 
         // Section 2.1.3: enclosed when s = Omega / 4 pi >= T; later surfaces win.
 #pragma unroll

@@ -14,9 +14,25 @@ struct sal_context {
     int64_t flag_cap = 0;
     unsigned long long *counters = nullptr;  // sal::kNumCounters
     int n_cu = 0;
+    // batched form
+    void *batch_items = nullptr;
+    int64_t batch_items_bytes = 0;
+    void *batch_insts = nullptr;
+    int64_t batch_insts_bytes = 0;
+    double *batch_partial = nullptr;
+    uint64_t *batch_mask = nullptr;
+    int64_t batch_slots = 0;
+    unsigned int *batch_next = nullptr;
+    unsigned long long *batch_counters = nullptr;
+    int64_t batch_counters_n = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t batch_graph = nullptr;
+    uint64_t batch_graph_key = 0;
+    int64_t batch_graph_points = 0;
 };
 
 struct sal_surface_set {
+    uint64_t uid = 0;      // unique per creation (graph cache keys)
     int device = 0;
     int n_surf = 0;
     int64_t n_tri = 0, n_strips = 0, n_rec = 0, bytes = 0;
@@ -25,6 +41,8 @@ struct sal_surface_set {
     sal::SurfaceDev *surf = nullptr;
     int64_t *strip_off = nullptr;
     std::vector<sal::SurfaceDev> host_table;
+    std::vector<int64_t> host_strip_off;   // record index of every strip head
+    std::vector<int32_t> host_strip_tris;  // triangles of every strip
 };
 
 namespace sal {

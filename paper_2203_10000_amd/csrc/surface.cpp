@@ -2,6 +2,7 @@
 // triangle strips, float32 / float64 strip records on the device.
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <unordered_map>
 
 #include "runtime.h"
@@ -178,6 +179,7 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
     std::vector<Rec32> r32;
     std::vector<Rec64> r64;
     std::vector<int64_t> strip_off;
+    std::vector<int32_t> strip_tris;
     std::vector<SurfaceDev> table((size_t)n);
     int64_t total_tri = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -204,6 +206,7 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
         for (const Strip &s : strips) {
             strip_off.push_back((int64_t)r32.size());
             const int m = (int)s.tris.size();
+            strip_tris.push_back(m);
             Rec32 h32{};
             Rec64 h64{};
             for (int c = 0; c < 3; ++c) {
@@ -250,13 +253,17 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
     }
 
     SAL_HIP(hipSetDevice(ctx->device));
+    static std::atomic<uint64_t> next_uid{1};
     auto *set = new sal_surface_set();
+    set->uid = next_uid++;
     set->device = ctx->device;
     set->n_surf = n;
     set->n_tri = total_tri;
     set->n_strips = (int64_t)strip_off.size();
     set->n_rec = (int64_t)r32.size();
     set->host_table = table;
+    set->host_strip_off = strip_off;
+    set->host_strip_tris = strip_tris;
     sal_status st = SAL_OK;
     auto up = [&](void **dst, const void *src, size_t bytes) -> sal_status {
         hipError_t e = hipMalloc(dst, bytes);
