@@ -37,6 +37,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2 (default, the benchmark line); c3 refine-and-relabel, c4 batched, "
+                         "c5 precision stress: measurement lines for the design notes")
+    ap.add_argument("--c5-lattice-fraction", type=float, default=0.125,
+                    help="c5: fraction of the 0.5 mm lattice (a slab along z) to label")
+    ap.add_argument("--check-sample", type=int, default=20000,
+                    help="c3/c4/c5: points checked against the FP64 oracle")
     return ap.parse_args()
 
 
@@ -109,6 +116,157 @@ def cpu_model():
     return "unknown"
 
 
+def _oracle_check(pts_np, surfaces, gpu_labels_np, n, rng, near_mask=None):
+    """Labels of a sample (uniform + near-surface) against the FP64 oracle."""
+    import numpy as np
+    import oracle
+    idx = rng.choice(pts_np.shape[1], min(n, pts_np.shape[1]), replace=False)
+    if near_mask is not None and near_mask.any():
+        near = np.nonzero(near_mask)[0]
+        idx = np.unique(np.concatenate([idx, rng.choice(near, min(n, len(near)), replace=False)]))
+    want = oracle.label(np.ascontiguousarray(pts_np[:, idx]), surfaces)
+    return int((gpu_labels_np[idx] != want).sum()), int(len(idx))
+
+
+def run_c3(args):
+    """c3: 20 compartments (4 x 81,920 + 16 x 5,120 triangles), 1 mm lattice
+    (48M centroids), two refine-and-relabel rounds in FP32 + recheck."""
+    import numpy as np
+    import torch
+    import paper_2203_10000_amd as sal
+    import synth
+    cfg = synth.config_c3()
+    lat = cfg.lattice
+    ctx = sal.Context(0)
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = mesh.refine_relabel(ss, cfg.rounds, precision="fp32")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pairs = sum(r["n_pairs"] for r in st)
+    n_leaves, lv = mesh.size()
+    e = mesh.export(keys=False, labels=True, centroids=True)
+    lab = e["labels"].cpu().numpy()
+    cen = e["centroids"].cpu().numpy()
+    del e
+    rng = np.random.default_rng(33)
+    r = np.linalg.norm(cen.astype(np.float64), axis=0)
+    near = np.min(np.abs(r[:, None] - np.array([92, 86, 80, 76.0])), axis=1) < 4.0
+    mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, near)
+    return {"workload": "c3", "triangles": cfg.n_tri, "rounds": st, "leaves": n_leaves,
+            "max_level": lv, "pairs": pairs, "wall_s": wall,
+            "g_pairs_per_s": pairs / wall / 1e9,
+            "leaf_count_identity": n_leaves == lat.n_points + 7 * sum(x["n_boundary"] for x in st),
+            "oracle_sample_mismatches": mism, "oracle_sample": checked}
+
+
+def run_c4(args):
+    """c4: 64 instances, batched persistent launch (eager and hipGraph replay)
+    against 64 per-instance launches."""
+    import numpy as np
+    import torch
+    import paper_2203_10000_amd as sal
+    import synth
+    insts = synth.config_c4()
+    ctx = sal.Context(0)
+    dev = []
+    pairs = 0
+    for surfs, pts in insts:
+        ss = sal.SurfaceSet(ctx, surfs)
+        p = torch.from_numpy(pts).to("cuda:0")
+        dev.append((ss, p, torch.empty(pts.shape[1], dtype=torch.int32, device="cuda:0")))
+        pairs += pts.shape[1] * sum(s.n_tri for s in surfs)
+    out = {"workload": "c4", "instances": len(insts), "pairs": pairs,
+           "points": int(sum(p.shape[1] for _, p in insts))}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    per = [torch.empty_like(l) for _, _, l in dev]
+
+    def per_instance():
+        for (ss, p, _), l in zip(dev, per):
+            sal.label_points(ctx, ss, p, out=l)
+
+    t_per = timed(per_instance, 2)
+    t_batch = timed(lambda: sal.label_batch(ctx, dev), 2)
+    t_graph = timed(lambda: sal.label_batch(ctx, dev, use_graph=True), 3)
+    same = all(torch.equal(a, l) for a, (_, _, l) in zip(per, dev))
+    rng = np.random.default_rng(44)
+    mism = checked = 0
+    for (surfs, pts), (_, _, l) in list(zip(insts, dev))[:16]:
+        m, c = _oracle_check(pts, surfs, l.cpu().numpy(), args.check_sample // 16, rng)
+        mism += m
+        checked += c
+    out.update({"per_instance": {"s": t_per, "g_pairs_per_s": pairs / t_per / 1e9},
+                "batched": {"s": t_batch, "g_pairs_per_s": pairs / t_batch / 1e9},
+                "batched_graph": {"s": t_graph, "g_pairs_per_s": pairs / t_graph / 1e9},
+                "batched_equals_per_instance": bool(same),
+                "oracle_sample_mismatches": mism, "oracle_sample": checked})
+    return out
+
+
+def run_c5(args):
+    """c5: 8 x 297,680-triangle compartments; 2e7 points offset U[-0.5, 0.5] mm
+    along face normals plus a z-slab of the 0.5 mm lattice; recheck fraction
+    and oracle mismatches."""
+    import numpy as np
+    import torch
+    import paper_2203_10000_amd as sal
+    import synth
+    cfg = synth.config_c5()
+    lat = cfg.lattice
+    ctx = sal.Context(0)
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    out = {"workload": "c5", "triangles": cfg.n_tri, "lattice_cells": lat.cells}
+    near = torch.from_numpy(cfg.points).to("cuda:0")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lab, _, st = sal.label_points(ctx, ss, near, stats=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    rng = np.random.default_rng(55)
+    mism, checked = _oracle_check(cfg.points, cfg.surfaces, lab.cpu().numpy(), args.check_sample, rng)
+    out["near_surface"] = {"points": int(near.shape[1]), "pairs": st["n_pairs"], "wall_s": wall,
+                           "g_pairs_per_s": st["n_pairs"] / wall / 1e9,
+                           "recheck_points": st["n_recheck_points"],
+                           "recheck_pairs": st["n_recheck_pairs"],
+                           "band_flags": st["n_band_flags"], "cond_flags": st["n_cond_flags"],
+                           "exact_fallbacks": st["n_exact_fallbacks"],
+                           "ms_pairloop": st["ms_pairloop"], "ms_recheck": st["ms_recheck"],
+                           "oracle_sample_mismatches": mism, "oracle_sample": checked}
+    del near, lab
+    nz = max(1, int(round(lat.cells[2] * args.c5_lattice_fraction)))
+    z0 = (lat.cells[2] - nz) // 2
+    slab = (lat.cells[0], lat.cells[1], nz)
+    origin = (lat.origin[0], lat.origin[1], lat.origin[2] + lat.h * z0)
+    mesh = sal.TetMesh(ctx, origin, lat.h, slab)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rs = mesh.refine_relabel(ss, 0, precision="fp32")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    e = mesh.export(keys=False, labels=True, centroids=True)
+    cen = e["centroids"].cpu().numpy()
+    lab = e["labels"].cpu().numpy()
+    r = np.linalg.norm(cen.astype(np.float64), axis=0)
+    nearm = np.min(np.abs(r[:, None] - np.array([92, 86, 80, 76.0])), axis=1) < 3.0
+    mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, nearm)
+    out["lattice_slab"] = {"cells": slab, "points": rs[0]["n_labeled"], "pairs": rs[0]["n_pairs"],
+                           "wall_s": wall, "g_pairs_per_s": rs[0]["n_pairs"] / wall / 1e9,
+                           "recheck_pairs": rs[0]["n_recheck_pairs"],
+                           "oracle_sample_mismatches": mism, "oracle_sample": checked}
+    return out
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -123,6 +281,12 @@ def main():
     import torch
     import paper_2203_10000_amd as sal
     import synth
+
+    if args.workload != "c2":
+        torch.cuda.set_device(0)
+        fn = {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload]
+        print(json.dumps(fn(args), default=float), flush=True)
+        return
 
     cfg = synth.config_c2()
     lat = cfg.lattice
