@@ -60,8 +60,11 @@ def calibrate_copy():
 
 
 def source_digest():
-    p = os.path.join(ROOT, "paper_2203_10000_amd", "csrc", "pairloop.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the float32 pair-loop sources (kernel and its strip walk)."""
+    h = hashlib.sha256()
+    for name in ("pairloop.hip", "pairloop_f32.h"):
+        h.update(open(os.path.join(ROOT, "paper_2203_10000_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def hbm_traffic(pairloop_launch_pairs):
