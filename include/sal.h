@@ -136,7 +136,13 @@ typedef struct sal_label_options {
     double recheck_band;      /* default 1e-3 */
     double kappa;             /* float32 conditioning threshold; 0 = 2^-5 */
     int32_t points_per_lane;  /* 0 = tuned; else 1, 2 or 4 */
-    int32_t block_waves;      /* 0 = tuned; else 1, 2, 4 or 8 wavefronts per block */
+    int32_t block_waves;      /* 0 = tuned; else 1, 2, 4 or 8 wavefronts per block.
+                                 Tuned: the first call for a (device, precision,
+                                 log2 triangles, log2 points) times every candidate
+                                 on up to 2^19 of the points (synchronising the
+                                 stream) and caches the fastest for the process,
+                                 and in the file named by SAL_TUNE_CACHE if set;
+                                 SAL_TUNE=0 disables tuning (1 point, 4 waves). */
     int32_t use_graph;        /* sal_label_batch: 1 = capture the launch sequence in a
                                  hipGraph and replay it while the same instances (same
                                  surface sets, pointers, sizes, options) come back */
@@ -156,6 +162,8 @@ typedef struct sal_label_stats {
     float ms_pairloop;         /* device time of the pair loop */
     float ms_recheck;          /* device time of the FP64 recheck */
     float ms_total;            /* device time from first to last kernel */
+    int32_t points_per_lane;   /* launch shape used (chosen by the tuner when 0 was asked) */
+    int32_t block_waves;
 } sal_label_stats;
 
 /* Labels n_points points (section 2.1.3: s = Omega / 4 pi, enclosed when

@@ -55,7 +55,8 @@ class LabelStats(ctypes.Structure):
                 ("n_recheck_points", ctypes.c_int64), ("n_recheck_pairs", ctypes.c_int64),
                 ("n_band_flags", ctypes.c_int64), ("n_cond_flags", ctypes.c_int64),
                 ("n_exact_fallbacks", ctypes.c_int64), ("ms_pairloop", ctypes.c_float),
-                ("ms_recheck", ctypes.c_float), ("ms_total", ctypes.c_float)]
+                ("ms_recheck", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("points_per_lane", ctypes.c_int32), ("block_waves", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

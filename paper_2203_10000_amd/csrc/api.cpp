@@ -47,19 +47,25 @@ sal_status resolve_options(const sal_label_options *in, sal_label_options *out) 
     if (out->kappa == 0.0) out->kappa = 0.03125;
     if (!(out->kappa > 0.0 && out->kappa < 1.0))
         return set_error(SAL_ERR_INVALID_ARG, "kappa must be in (0, 1)");
-    if (out->points_per_lane == 0) out->points_per_lane = 1;
-    if (out->points_per_lane != 1 && out->points_per_lane != 2 && out->points_per_lane != 4)
+    if (out->points_per_lane != 0 && out->points_per_lane != 1 && out->points_per_lane != 2 &&
+        out->points_per_lane != 4)
         return set_error(SAL_ERR_INVALID_ARG, "points_per_lane must be 0, 1, 2 or 4");
-    if (out->block_waves == 0) out->block_waves = 4;
-    if (out->block_waves != 1 && out->block_waves != 2 && out->block_waves != 4 &&
+    if (out->block_waves != 0 && out->block_waves != 1 && out->block_waves != 2 && out->block_waves != 4 &&
         out->block_waves != 8)
         return set_error(SAL_ERR_INVALID_ARG, "block_waves must be 0, 1, 2, 4 or 8");
     return SAL_OK;
 }
 
 sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
-                         const float *y, const float *z, const sal_label_options &opt,
-                         int32_t *labels, void *winding, hipEvent_t ev_mid) {
+                         const float *y, const float *z, const sal_label_options &opt_in,
+                         int32_t *labels, void *winding, hipEvent_t ev_mid, int *shape) {
+    sal_label_options opt = opt_in;
+    sal_status ts = tune_launch(ctx, set, n, x, y, z, labels, &opt);
+    if (ts != SAL_OK) return ts;
+    if (shape) {
+        shape[0] = opt.points_per_lane;
+        shape[1] = opt.block_waves;
+    }
     PairloopArgs a{};
     a.rec32 = set->rec32;
     a.rec64 = set->rec64;
@@ -176,6 +182,8 @@ sal_status sal_context_create(int device, void *stream, sal_context **out) {
     }
     e = hipMalloc((void **)&ctx->counters, kNumCounters * sizeof(unsigned long long));
     if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(counters)"); }
+    e = hipMalloc((void **)&ctx->tune_counters, kNumCounters * sizeof(unsigned long long));
+    if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(counters)"); }
     e = hipMalloc((void **)&ctx->batch_next, sizeof(unsigned int) * 4);
     if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(batch counter)"); }
     e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
@@ -199,6 +207,7 @@ void sal_context_destroy(sal_context *ctx) {
         if (ev) (void)hipEventDestroy(ev);
     if (ctx->flag_list) (void)hipFree(ctx->flag_list);
     if (ctx->counters) (void)hipFree(ctx->counters);
+    if (ctx->tune_counters) (void)hipFree(ctx->tune_counters);
     if (ctx->batch_graph) (void)hipGraphExecDestroy(ctx->batch_graph);
     if (ctx->batch_items) (void)hipFree(ctx->batch_items);
     if (ctx->batch_insts) (void)hipFree(ctx->batch_insts);
@@ -257,7 +266,9 @@ sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_
     }
     SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, ctx->stream));
     if (stats) SAL_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
-    st = enqueue_label(ctx, set, n, x, y, z, opt, labels, winding, stats ? ctx->ev[1] : nullptr);
+    int shape[2] = {0, 0};
+    st = enqueue_label(ctx, set, n, x, y, z, opt, labels, winding, stats ? ctx->ev[1] : nullptr,
+                       shape);
     if (st != SAL_OK) return st;
     if (stats) {
         SAL_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
@@ -274,6 +285,8 @@ sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_
         SAL_HIP(hipEventElapsedTime(&stats->ms_pairloop, ctx->ev[0], ctx->ev[1]));
         SAL_HIP(hipEventElapsedTime(&stats->ms_total, ctx->ev[0], ctx->ev[2]));
         stats->ms_recheck = stats->ms_total - stats->ms_pairloop;
+        stats->points_per_lane = shape[0];
+        stats->block_waves = shape[1];
     }
     return SAL_OK;
     SAL_GUARD_END

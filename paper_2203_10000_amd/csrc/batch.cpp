@@ -292,6 +292,8 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
                 stats[i].n_exact_fallbacks = (int64_t)ci[kCntExact];
                 stats[i].ms_total = ms;   // the whole batch (one launch sequence)
                 stats[i].ms_pairloop = ms;
+                stats[i].points_per_lane = 1;   // one point per lane, 4 wavefronts per workgroup
+                stats[i].block_waves = 4;
             }
         }
         return SAL_OK;

@@ -13,6 +13,7 @@ struct sal_context {
     sal::FlagEntry *flag_list = nullptr;
     int64_t flag_cap = 0;
     unsigned long long *counters = nullptr;  // sal::kNumCounters
+    unsigned long long *tune_counters = nullptr;
     int n_cu = 0;
     // batched form
     void *batch_items = nullptr;
@@ -62,6 +63,12 @@ sal_status resolve_options(const sal_label_options *in, sal_label_options *out);
 // (after the pair loop) when non-null.
 sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
                          const float *y, const float *z, const sal_label_options &opt,
-                         int32_t *labels, void *winding, hipEvent_t ev_after_pairloop);
+                         int32_t *labels, void *winding, hipEvent_t ev_after_pairloop,
+                         int *shape = nullptr);
+
+// Resolves points_per_lane / block_waves left at 0 by timing the candidates
+// (first use of a size bucket synchronises the stream), cached per process.
+sal_status tune_launch(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
+                       const float *y, const float *z, int32_t *labels, sal_label_options *opt);
 
 }  // namespace sal

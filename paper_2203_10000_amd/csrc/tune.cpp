@@ -1,0 +1,150 @@
+// Launch-shape tuner for the pair loop: points per lane x wavefronts per
+// workgroup, timed on the device the first time a (device, precision,
+// triangle-count bucket, point-count bucket) is seen, then cached for the
+// process (and in the file named by SAL_TUNE_CACHE, if set).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "runtime.h"
+
+namespace sal {
+namespace {
+
+using Key = std::tuple<int, int, int, int, std::string, int, int>;
+
+std::mutex g_mu;
+std::map<Key, std::pair<int, int>> g_cache;
+bool g_loaded = false;
+
+int bucket(int64_t v) {
+    int b = 0;
+    while (v > 1 && b < 62) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+std::string arch_name(int device) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+    return std::string(p.gcnArchName);
+}
+
+void load_file() {
+    g_loaded = true;
+    const char *path = std::getenv("SAL_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[128];
+    int dev, prec, tb, nb, rp, rb, ppl, bw;
+    while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %d", arch, &dev, &prec, &tb, &nb, &rp, &rb,
+                       &ppl, &bw) == 9)
+        g_cache[Key(dev, prec, tb, nb, arch, rp, rb)] = {ppl, bw};
+    std::fclose(f);
+}
+
+void save_file() {
+    const char *path = std::getenv("SAL_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    for (const auto &kv : g_cache)
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", std::get<4>(kv.first).c_str(),
+                     std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                     std::get<3>(kv.first), std::get<5>(kv.first), std::get<6>(kv.first),
+                     kv.second.first, kv.second.second);
+    std::fclose(f);
+}
+
+}  // namespace
+
+// Fills opt->points_per_lane / opt->block_waves when they are 0 (auto).
+sal_status tune_launch(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
+                       const float *y, const float *z, int32_t *labels, sal_label_options *opt) {
+    const bool fp64 = opt->precision == SAL_PREC_FP64;
+    if (fp64) opt->points_per_lane = 1;
+    if (opt->points_per_lane != 0 && opt->block_waves != 0) return SAL_OK;
+    const char *off = std::getenv("SAL_TUNE");
+    if ((off && std::strcmp(off, "0") == 0) || n <= 0) {
+        if (opt->points_per_lane == 0) opt->points_per_lane = 1;
+        if (opt->block_waves == 0) opt->block_waves = 4;
+        return SAL_OK;
+    }
+    const Key key(ctx->device, opt->precision, bucket(set->n_tri), bucket(n), arch_name(ctx->device),
+                  opt->points_per_lane, opt->block_waves);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_loaded) load_file();
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            if (opt->points_per_lane == 0) opt->points_per_lane = it->second.first;
+            if (opt->block_waves == 0) opt->block_waves = it->second.second;
+            return SAL_OK;
+        }
+    }
+    // Trial launches of the pair loop alone on a prefix of the points (enough
+    // workgroups to fill the device several times), writing labels that the
+    // real launch overwrites.
+    const int64_t trial_n = n < ((int64_t)1 << 19) ? n : ((int64_t)1 << 19);
+    PairloopArgs a{};
+    a.rec32 = set->rec32;
+    a.rec64 = set->rec64;
+    a.surf = set->surf;
+    a.n_surf = set->n_surf;
+    a.x = x;
+    a.y = y;
+    a.z = z;
+    a.n = trial_n;
+    a.kappa = (float)opt->kappa;
+    a.threshold = opt->threshold;
+    a.band = opt->recheck_band;
+    a.labels = labels;
+    a.winding = nullptr;
+    a.winding_type = SAL_WINDING_NONE;
+    a.flag_list = ctx->flag_list;      // overwritten by the real launch
+    a.counters = ctx->tune_counters;   // the call's own counters stay untouched
+    const int ppls[3] = {1, 2, 4};
+    const int bws[4] = {1, 2, 4, 8};
+    float best = 1e30f;
+    int best_p = 1, best_b = 4;
+    for (int pi = 0; pi < (fp64 ? 1 : 3); ++pi) {
+        const int p = fp64 ? 1 : ppls[pi];
+        if (opt->points_per_lane != 0 && opt->points_per_lane != p) continue;
+        for (int b : bws) {
+            if (opt->block_waves != 0 && opt->block_waves != b) continue;
+            float t_min = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                SAL_HIP(launch_fill_u64(ctx->tune_counters, 0ull, kNumCounters, ctx->stream));
+                SAL_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
+                SAL_HIP(fp64 ? launch_pairloop_f64(a, b, ctx->stream)
+                             : launch_pairloop_f32(a, p, b, ctx->stream));
+                SAL_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
+                SAL_HIP(hipEventSynchronize(ctx->ev[6]));
+                float ms = 0.0f;
+                SAL_HIP(hipEventElapsedTime(&ms, ctx->ev[5], ctx->ev[6]));
+                if (ms < t_min) t_min = ms;
+            }
+            if (t_min < best) {
+                best = t_min;
+                best_p = p;
+                best_b = b;
+            }
+        }
+    }
+    if (opt->points_per_lane == 0) opt->points_per_lane = best_p;
+    if (opt->block_waves == 0) opt->block_waves = best_b;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[key] = {opt->points_per_lane, opt->block_waves};
+    save_file();
+    return SAL_OK;
+}
+
+}  // namespace sal

@@ -152,6 +152,21 @@ def test_winding_f32_output(ctx, head_small):
     assert np.max(np.abs(w - w_ref)) < 2e-5
 
 
+def test_tuner_picks_a_shape_and_caches_it(ctx, head_small, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("SAL_TUNE_CACHE", str(cache))
+    cfg, pts, want, _ = head_small
+    sub = np.ascontiguousarray(pts[:, :3000])          # a point-count bucket no other test uses
+    for prec in ("fp32", "fp64"):
+        got, _, st = run(ctx, cfg.surfaces, sub, precision=prec)
+        assert np.array_equal(got, want[:3000])
+        assert st["points_per_lane"] in (1, 2, 4) and st["block_waves"] in (1, 2, 4, 8)
+        got2, _, st2 = run(ctx, cfg.surfaces, sub, precision=prec)
+        assert np.array_equal(got2, got)
+        assert (st2["points_per_lane"], st2["block_waves"]) == (st["points_per_lane"], st["block_waves"])
+    assert cache.exists() and len(cache.read_text().splitlines()) >= 2
+
+
 # ---------------------------------------------------------------- validation
 def _sphere(subdiv=2, r=50.0):
     v, f = synth.icosphere(subdiv)
