@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--c5-lattice-fraction", type=float, default=0.125,
                     help="c5: fraction of the 0.5 mm lattice (a slab along z) to label")
     ap.add_argument("--check-sample", type=int, default=20000,
-                    help="c3/c4/c5: points checked against the FP64 oracle")
+                    help="c3/c4: points checked against the FP64 oracle")
+    ap.add_argument("--c5-check", type=int, default=2000,
+                    help="c5: points checked against the FP64 oracle (2.4M triangles each)")
     return ap.parse_args()
 
 
@@ -119,10 +121,16 @@ def cpu_model():
     return "unknown"
 
 
+def progress(msg):
+    """Phase line on stderr (long measurement runs print as they go)."""
+    print("[%s] %s" % (time.strftime("%H:%M:%S"), msg), file=sys.stderr, flush=True)
+
+
 def _oracle_check(pts_np, surfaces, gpu_labels_np, n, rng, near_mask=None):
     """Labels of a sample (uniform + near-surface) against the FP64 oracle."""
     import numpy as np
     import oracle
+    progress("oracle check of %d (+%d near) points" % (n, n if near_mask is not None else 0))
     idx = rng.choice(pts_np.shape[1], min(n, pts_np.shape[1]), replace=False)
     if near_mask is not None and near_mask.any():
         near = np.nonzero(near_mask)[0]
@@ -138,8 +146,10 @@ def run_c3(args):
     import torch
     import paper_2203_10000_amd as sal
     import synth
+    progress("c3: generating surfaces")
     cfg = synth.config_c3()
     lat = cfg.lattice
+    progress("c3: labeling and refining")
     ctx = sal.Context(0)
     ss = sal.SurfaceSet(ctx, cfg.surfaces)
     mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
@@ -172,8 +182,10 @@ def run_c4(args):
     import torch
     import paper_2203_10000_amd as sal
     import synth
+    progress("c4: generating 64 instances")
     insts = synth.config_c4()
     ctx = sal.Context(0)
+    progress("c4: timing")
     dev = []
     pairs = 0
     for surfs, pts in insts:
@@ -225,9 +237,11 @@ def run_c5(args):
     import torch
     import paper_2203_10000_amd as sal
     import synth
+    progress("c5: generating surfaces and points")
     cfg = synth.config_c5()
     lat = cfg.lattice
     ctx = sal.Context(0)
+    progress("c5: near-surface points")
     ss = sal.SurfaceSet(ctx, cfg.surfaces)
     out = {"workload": "c5", "triangles": cfg.n_tri, "lattice_cells": lat.cells}
     near = torch.from_numpy(cfg.points).to("cuda:0")
@@ -237,7 +251,7 @@ def run_c5(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     rng = np.random.default_rng(55)
-    mism, checked = _oracle_check(cfg.points, cfg.surfaces, lab.cpu().numpy(), args.check_sample, rng)
+    mism, checked = _oracle_check(cfg.points, cfg.surfaces, lab.cpu().numpy(), args.c5_check, rng)
     out["near_surface"] = {"points": int(near.shape[1]), "pairs": st["n_pairs"], "wall_s": wall,
                            "g_pairs_per_s": st["n_pairs"] / wall / 1e9,
                            "recheck_points": st["n_recheck_points"],
@@ -247,6 +261,7 @@ def run_c5(args):
                            "ms_pairloop": st["ms_pairloop"], "ms_recheck": st["ms_recheck"],
                            "oracle_sample_mismatches": mism, "oracle_sample": checked}
     del near, lab
+    progress("c5: lattice slab")
     nz = max(1, int(round(lat.cells[2] * args.c5_lattice_fraction)))
     z0 = (lat.cells[2] - nz) // 2
     slab = (lat.cells[0], lat.cells[1], nz)
@@ -262,7 +277,7 @@ def run_c5(args):
     lab = e["labels"].cpu().numpy()
     r = np.linalg.norm(cen.astype(np.float64), axis=0)
     nearm = np.min(np.abs(r[:, None] - np.array([92, 86, 80, 76.0])), axis=1) < 3.0
-    mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, nearm)
+    mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.c5_check, rng, nearm)
     out["lattice_slab"] = {"cells": slab, "points": rs[0]["n_labeled"], "pairs": rs[0]["n_pairs"],
                            "wall_s": wall, "g_pairs_per_s": rs[0]["n_pairs"] / wall / 1e9,
                            "recheck_pairs": rs[0]["n_recheck_pairs"],

@@ -211,7 +211,7 @@ typedef struct sal_refine_stats {
     int64_t n_labeled;    /* points labeled this round */
     int64_t n_pairs;      /* n_labeled x total triangles */
     int64_t n_recheck_pairs;
-    float ms_mark, ms_compact, ms_split, ms_label, ms_total;
+    float ms_mark, ms_compact, ms_split, ms_label, ms_recheck, ms_total;
 } sal_refine_stats;
 
 /* Section 2.1.3: labels every unlabeled leaf (round 0: the whole lattice),

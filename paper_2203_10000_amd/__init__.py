@@ -67,7 +67,8 @@ class RefineStats(ctypes.Structure):
                 ("n_labeled", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("n_recheck_pairs", ctypes.c_int64), ("ms_mark", ctypes.c_float),
                 ("ms_compact", ctypes.c_float), ("ms_split", ctypes.c_float),
-                ("ms_label", ctypes.c_float), ("ms_total", ctypes.c_float)]
+                ("ms_label", ctypes.c_float), ("ms_recheck", ctypes.c_float),
+                ("ms_total", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

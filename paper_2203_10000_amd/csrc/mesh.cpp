@@ -135,9 +135,10 @@ sal_status compact(sal_tet_mesh *m, const CompactSrc &src, int64_t n, int32_t *o
     return SAL_OK;
 }
 
-// Labels n points whose centroids sit in the scratch into `labels`.
+// Labels n points whose centroids sit in the scratch into `labels`; records
+// ev_mid after the pair loop (before the recheck).
 sal_status label_scratch(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set, int64_t n,
-                         const sal_label_options &opt, int32_t *labels) {
+                         const sal_label_options &opt, int32_t *labels, hipEvent_t ev_mid) {
     if (n <= 0) return SAL_OK;
     if (opt.precision == SAL_PREC_FP32_RECHECK) {
         sal_status st = ensure_flag_capacity(ctx, n);
@@ -145,7 +146,7 @@ sal_status label_scratch(sal_context *ctx, sal_tet_mesh *m, const sal_surface_se
     }
     SAL_HIP(launch_fill_u64(ctx->counters + kCntFlagged, 0ull, 1, ctx->stream));
     return enqueue_label(ctx, set, n, m->cen[0], m->cen[1], m->cen[2], opt, labels, nullptr,
-                         nullptr);
+                         ev_mid);
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -257,9 +258,12 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
         if (!m->labeled0) {
             if ((st = ensure_centroids(m, m->n[0], s)) != SAL_OK) return st;
             SAL_HIP(launch_lattice_centroids(m->g, m->n[0], m->cen[0], m->cen[1], m->cen[2], s));
-            if ((st = label_scratch(ctx, m, set, m->n[0], opt, m->label[0])) != SAL_OK) return st;
+            if ((st = label_scratch(ctx, m, set, m->n[0], opt, m->label[0], m->ev[9])) != SAL_OK)
+                return st;
             m->labeled0 = true;
             labeled0 = m->n[0];
+        } else {
+            SAL_HIP(hipEventRecord(m->ev[9], s));
         }
         SAL_HIP(hipEventRecord(m->ev[1], s));
         if (per_round) {
@@ -270,8 +274,9 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
             r0.n_labeled = labeled0;
             r0.n_pairs = labeled0 * set->n_tri;
             r0.n_recheck_pairs = (int64_t)cnt[kCntRecheck];
-            r0.ms_label = elapsed(m->ev[0], m->ev[1]);
-            r0.ms_total = r0.ms_label;
+            r0.ms_label = elapsed(m->ev[0], m->ev[9]);
+            r0.ms_recheck = elapsed(m->ev[9], m->ev[1]);
+            r0.ms_total = elapsed(m->ev[0], m->ev[1]);
         }
 
         for (int r = 1; r <= rounds; ++r) {
@@ -300,7 +305,7 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
             if (top == kMaxLevels && count[top] > 0)
                 return set_error(SAL_ERR_CAPACITY, "refinement beyond level 3");
             int64_t n_split = 0, n_label = 0;
-            float ms_split = 0.0f, ms_label = 0.0f;
+            float ms_split = 0.0f, ms_label = 0.0f, ms_recheck = 0.0f;
             // deepest level first: its children array never moves under a
             // pending split of a coarser level
             for (int l = top; l >= 0; --l) {
@@ -315,13 +320,14 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
                                      m->cen[0], m->cen[1], m->cen[2], s));
                 SAL_HIP(hipEventRecord(m->ev[6], s));
                 m->n[l + 1] += kids;
-                if ((st = label_scratch(ctx, m, set, kids, opt, m->label[l + 1] + 8 * base_block)) !=
-                    SAL_OK)
+                if ((st = label_scratch(ctx, m, set, kids, opt, m->label[l + 1] + 8 * base_block,
+                                        m->ev[9])) != SAL_OK)
                     return st;
                 SAL_HIP(hipEventRecord(m->ev[7], s));
                 SAL_HIP(hipEventSynchronize(m->ev[7]));
                 ms_split += elapsed(m->ev[5], m->ev[6]);
-                ms_label += elapsed(m->ev[6], m->ev[7]);
+                ms_label += elapsed(m->ev[6], m->ev[9]);
+                ms_recheck += elapsed(m->ev[9], m->ev[7]);
                 if (l + 1 > m->max_level) m->max_level = l + 1;
                 n_split += count[l];
                 n_label += kids;
@@ -341,6 +347,7 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
                 rs.ms_compact = elapsed(m->ev[3], m->ev[4]);
                 rs.ms_split = ms_split;
                 rs.ms_label = ms_label;
+                rs.ms_recheck = ms_recheck;
                 rs.ms_total = elapsed(m->ev[2], m->ev[8]);
             }
         }
