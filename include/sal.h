@@ -139,13 +139,18 @@ typedef struct sal_label_options {
     int32_t block_waves;      /* 0 = tuned; else 1, 2, 4 or 8 wavefronts per block.
                                  Tuned: the first call for a (device, precision,
                                  log2 triangles, log2 points) times every candidate
-                                 on up to 2^19 of the points (synchronising the
-                                 stream) and caches the fastest for the process,
-                                 and in the file named by SAL_TUNE_CACHE if set;
-                                 SAL_TUNE=0 disables tuning (1 point, 4 waves). */
+                                 on up to 2^19 of the points against the leading
+                                 strips of the set (about 32768 triangles, 8192 in
+                                 the FP64 form), synchronising the stream, and
+                                 caches the fastest for the process, and in the
+                                 file named by SAL_TUNE_CACHE if set; SAL_TUNE=0
+                                 disables tuning (1 point, 4 waves). */
     int32_t use_graph;        /* sal_label_batch: 1 = capture the launch sequence in a
                                  hipGraph and replay it while the same instances (same
-                                 surface sets, pointers, sizes, options) come back */
+                                 surface sets, pointers, sizes, options) come back;
+                                 sal_refine_relabel: 1 = run the rounds as launches of
+                                 one captured round graph (see there);
+                                 sal_label_points ignores it */
 } sal_label_options;
 
 /* Fills the defaults listed above. */
@@ -161,7 +166,8 @@ typedef struct sal_label_stats {
     int64_t n_exact_fallbacks; /* triangle evaluations that needed the exact sign */
     float ms_pairloop;         /* device time of the pair loop */
     float ms_recheck;          /* device time of the FP64 recheck */
-    float ms_total;            /* device time from first to last kernel */
+    float ms_total;            /* device time from the pair loop's start to the
+                                  last kernel (launch-shape tuning excluded) */
     int32_t points_per_lane;   /* launch shape used (chosen by the tuner when 0 was asked) */
     int32_t block_waves;
 } sal_label_stats;
@@ -211,7 +217,14 @@ typedef struct sal_refine_stats {
     int64_t n_labeled;    /* points labeled this round */
     int64_t n_pairs;      /* n_labeled x total triangles */
     int64_t n_recheck_pairs;
+    /* device times; ms_label and ms_recheck leave out launch-shape tuning,
+       ms_total (the whole round) includes it.  A round run as a replay of
+       the captured round graph reports ms_total only. */
     float ms_mark, ms_compact, ms_split, ms_label, ms_recheck, ms_total;
+    int32_t graph;        /* 0: host-driven round; 1: launch of the round graph
+                             captured in this call; 2: launch of a round graph
+                             kept from an earlier call */
+    int32_t reserved;
 } sal_refine_stats;
 
 /* Section 2.1.3: labels every unlabeled leaf (round 0: the whole lattice),
@@ -219,8 +232,22 @@ typedef struct sal_refine_stats {
  * leaf of another label (faces on the domain boundary ignored), splits the
  * marked leaves 1 -> 8 and labels only the children.
  *   per_round  NULL, or [rounds + 1] filled after synchronising
- * Synchronises the stream once per round to size the new level.  Errors:
- * SAL_ERR_CAPACITY when a leaf would exceed refinement level 3. */
+ * Without opt->use_graph the host drives each round and synchronises the
+ * stream once per round to size the new level.  With opt->use_graph, once
+ * the lattice is labeled, the steps of one round (marking, compaction, split,
+ * labeling of the children with the FP64 recheck, commit of their labels)
+ * are captured once as a hipGraph that reads every size from device memory;
+ * the graph is launched `rounds` times back to back, with one synchronisation
+ * at the end, and kept on the mesh for later calls until a buffer it uses is
+ * reallocated.  Every level and the scratch are reserved up front for twice
+ * the current leaf count of new children per round, at least 2^20
+ * (device memory of about 60 bytes per reserved child; the environment
+ * variable SAL_REFINE_GRAPH_BUDGET overrides the count); a round that would not fit is
+ * stopped on the device before it changes the mesh, and that round and the
+ * rest run host-driven (growing the buffers).  A launch shape left at 0 is
+ * resolved before capture.  The leaves, their order and labels are the same
+ * in both modes.  Errors: SAL_ERR_CAPACITY when a leaf would exceed
+ * refinement level 3. */
 sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *mesh, const sal_surface_set *set,
                               int32_t rounds, const sal_label_options *opt,
                               sal_refine_stats *per_round);

@@ -68,7 +68,8 @@ class RefineStats(ctypes.Structure):
                 ("n_recheck_pairs", ctypes.c_int64), ("ms_mark", ctypes.c_float),
                 ("ms_compact", ctypes.c_float), ("ms_split", ctypes.c_float),
                 ("ms_label", ctypes.c_float), ("ms_recheck", ctypes.c_float),
-                ("ms_total", ctypes.c_float)]
+                ("ms_total", ctypes.c_float), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -56,16 +56,10 @@ sal_status resolve_options(const sal_label_options *in, sal_label_options *out) 
     return SAL_OK;
 }
 
-sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
-                         const float *y, const float *z, const sal_label_options &opt_in,
-                         int32_t *labels, void *winding, hipEvent_t ev_mid, int *shape) {
-    sal_label_options opt = opt_in;
-    sal_status ts = tune_launch(ctx, set, n, x, y, z, labels, &opt);
-    if (ts != SAL_OK) return ts;
-    if (shape) {
-        shape[0] = opt.points_per_lane;
-        shape[1] = opt.block_waves;
-    }
+sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_t n,
+                            const int64_t *n_dev, const float *x, const float *y, const float *z,
+                            const sal_label_options &opt, int32_t *labels, void *winding,
+                            hipEvent_t ev_mid, hipStream_t stream) {
     PairloopArgs a{};
     a.rec32 = set->rec32;
     a.rec64 = set->rec64;
@@ -75,6 +69,7 @@ sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n
     a.y = y;
     a.z = z;
     a.n = n;
+    a.n_dev = n_dev;
     a.kappa = (float)opt.kappa;
     a.threshold = opt.threshold;
     a.band = opt.recheck_band;
@@ -85,12 +80,12 @@ sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n
     a.flag_list = ctx->flag_list;
     a.counters = ctx->counters;
     if (opt.precision == SAL_PREC_FP64) {
-        SAL_HIP(launch_pairloop_f64(a, opt.block_waves, ctx->stream));
-        if (ev_mid) SAL_HIP(hipEventRecord(ev_mid, ctx->stream));
+        SAL_HIP(launch_pairloop_f64(a, opt.block_waves, stream));
+        if (ev_mid) SAL_HIP(hipEventRecord(ev_mid, stream));
         return SAL_OK;
     }
-    SAL_HIP(launch_pairloop_f32(a, opt.points_per_lane, opt.block_waves, ctx->stream));
-    if (ev_mid) SAL_HIP(hipEventRecord(ev_mid, ctx->stream));
+    SAL_HIP(launch_pairloop_f32(a, opt.points_per_lane, opt.block_waves, stream));
+    if (ev_mid) SAL_HIP(hipEventRecord(ev_mid, stream));
     RecheckArgs r{};
     r.rec64 = set->rec64;
     r.surf = set->surf;
@@ -106,8 +101,24 @@ sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n
     r.flag_list = ctx->flag_list;
     r.counters = ctx->counters;
     const int64_t grid = n < (int64_t)ctx->n_cu * 8 ? n : (int64_t)ctx->n_cu * 8;
-    SAL_HIP(launch_recheck_f64(r, (int)grid, ctx->stream));
+    SAL_HIP(launch_recheck_f64(r, (int)grid, stream));
     return SAL_OK;
+}
+
+sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
+                         const float *y, const float *z, const sal_label_options &opt_in,
+                         int32_t *labels, void *winding, hipEvent_t ev_start, hipEvent_t ev_mid,
+                         int *shape) {
+    sal_label_options opt = opt_in;
+    sal_status ts = tune_launch(ctx, set, n, x, y, z, labels, &opt);
+    if (ts != SAL_OK) return ts;
+    if (ev_start) SAL_HIP(hipEventRecord(ev_start, ctx->stream));
+    if (shape) {
+        shape[0] = opt.points_per_lane;
+        shape[1] = opt.block_waves;
+    }
+    return enqueue_label_on(ctx, set, n, nullptr, x, y, z, opt, labels, winding, ev_mid,
+                            ctx->stream);
 }
 
 }  // namespace sal
@@ -265,10 +276,9 @@ sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_
         if (st != SAL_OK) return st;
     }
     SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, ctx->stream));
-    if (stats) SAL_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
     int shape[2] = {0, 0};
-    st = enqueue_label(ctx, set, n, x, y, z, opt, labels, winding, stats ? ctx->ev[1] : nullptr,
-                       shape);
+    st = enqueue_label(ctx, set, n, x, y, z, opt, labels, winding, stats ? ctx->ev[0] : nullptr,
+                       stats ? ctx->ev[1] : nullptr, shape);
     if (st != SAL_OK) return st;
     if (stats) {
         SAL_HIP(hipEventRecord(ctx->ev[2], ctx->stream));

@@ -1,6 +1,9 @@
 // Tetrahedral mesh: Kuhn lattice creation, recursive refine-and-relabel
 // rounds (paper section 2.1.3 item 2), export of the leaves.
+#include <algorithm>
 #include <cmath>
+#include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -61,13 +64,19 @@ struct sal_tet_mesh {
     int64_t blocks_cap = 0;
     int64_t *totals = nullptr;   // kMaxLevels + 1 counts
     hipEvent_t ev[16] = {};
+    // captured refine round
+    int32_t *lab_scratch = nullptr;
+    int64_t lab_cap = 0;
+    sal::RoundState *rs = nullptr;
+    hipGraphExec_t round_graph = nullptr;
+    uint64_t round_key = 0;
 };
 
 namespace sal {
 namespace {
 
 sal::LevelPtrs ptrs(const sal_tet_mesh *m) {
-    LevelPtrs L;
+    LevelPtrs L{};   // n_dev stays null: host-driven sizes
     for (int l = 0; l <= kMaxLevels; ++l) {
         L.key[l] = m->key[l];
         L.label[l] = m->label[l];
@@ -136,9 +145,11 @@ sal_status compact(sal_tet_mesh *m, const CompactSrc &src, int64_t n, int32_t *o
 }
 
 // Labels n points whose centroids sit in the scratch into `labels`; records
-// ev_mid after the pair loop (before the recheck).
+// ev_start after any launch-shape tuning and ev_mid after the pair loop
+// (before the recheck).
 sal_status label_scratch(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set, int64_t n,
-                         const sal_label_options &opt, int32_t *labels, hipEvent_t ev_mid) {
+                         const sal_label_options &opt, int32_t *labels, hipEvent_t ev_start,
+                         hipEvent_t ev_mid) {
     if (n <= 0) return SAL_OK;
     if (opt.precision == SAL_PREC_FP32_RECHECK) {
         sal_status st = ensure_flag_capacity(ctx, n);
@@ -146,13 +157,290 @@ sal_status label_scratch(sal_context *ctx, sal_tet_mesh *m, const sal_surface_se
     }
     SAL_HIP(launch_fill_u64(ctx->counters + kCntFlagged, 0ull, 1, ctx->stream));
     return enqueue_label(ctx, set, n, m->cen[0], m->cen[1], m->cen[2], opt, labels, nullptr,
-                         ev_mid);
+                         ev_start, ev_mid);
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0f;
     return ms;
+}
+
+// One host-driven round (section 2.1.3 item 2): mark, compact, then for each
+// level, deepest first, split the marked leaves and label their children.
+// Synchronises once to size the new level (and once per level for timing).
+sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
+                       const sal_label_options &opt, sal_refine_stats *out) {
+    hipStream_t s = ctx->stream;
+    sal_status st;
+    const int top = m->max_level;
+    int64_t total_entries = 0;
+    for (int l = 0; l <= top; ++l) total_entries += m->n[l];
+    if ((st = ensure_buf(&m->list, &m->list_cap, total_entries, s)) != SAL_OK) return st;
+    SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, s));
+    SAL_HIP(hipEventRecord(m->ev[2], s));
+    for (int l = 0; l <= top; ++l) SAL_HIP(launch_fill_u8(m->flag[l], 0, m->n[l], s));
+    LevelPtrs L = ptrs(m);
+    for (int l = 0; l <= top; ++l) SAL_HIP(launch_mark(L, m->g, m->T, l, s));
+    SAL_HIP(hipEventRecord(m->ev[3], s));
+    int64_t off[kMaxLevels + 2] = {0};
+    for (int l = 0; l <= top; ++l) {
+        off[l + 1] = off[l] + m->n[l];
+        CompactSrc src{m->flag[l], nullptr};
+        if ((st = compact(m, src, m->n[l], m->list + off[l], m->totals + l, s)) != SAL_OK) return st;
+    }
+    SAL_HIP(hipEventRecord(m->ev[4], s));
+    int64_t count[kMaxLevels + 1] = {0};
+    SAL_HIP(hipMemcpyAsync(count, m->totals, sizeof(int64_t) * (top + 1), hipMemcpyDeviceToHost, s));
+    SAL_HIP(hipStreamSynchronize(s));
+    if (top == kMaxLevels && count[top] > 0)
+        return set_error(SAL_ERR_CAPACITY, "refinement beyond level 3");
+    int64_t n_split = 0, n_label = 0;
+    float ms_split = 0.0f, ms_label = 0.0f, ms_recheck = 0.0f;
+    // deepest level first: its children array never moves under a pending
+    // split of a coarser level
+    for (int l = top; l >= 0; --l) {
+        if (count[l] == 0) continue;
+        const int64_t kids = 8 * count[l];
+        if ((st = ensure_level(m, l + 1, m->n[l + 1] + kids, s)) != SAL_OK) return st;
+        if ((st = ensure_centroids(m, kids, s)) != SAL_OK) return st;
+        const int64_t base_block = m->n[l + 1] / 8;
+        LevelPtrs L2 = ptrs(m);
+        SAL_HIP(hipEventRecord(m->ev[5], s));
+        SAL_HIP(launch_split(L2, m->g, m->T, l, m->list + off[l], count[l], base_block, m->cen[0],
+                             m->cen[1], m->cen[2], s));
+        SAL_HIP(hipEventRecord(m->ev[6], s));
+        m->n[l + 1] += kids;
+        if ((st = label_scratch(ctx, m, set, kids, opt, m->label[l + 1] + 8 * base_block,
+                                m->ev[10], m->ev[9])) != SAL_OK)
+            return st;
+        SAL_HIP(hipEventRecord(m->ev[7], s));
+        SAL_HIP(hipEventSynchronize(m->ev[7]));
+        ms_split += elapsed(m->ev[5], m->ev[6]);
+        ms_label += elapsed(m->ev[10], m->ev[9]);
+        ms_recheck += elapsed(m->ev[9], m->ev[7]);
+        if (l + 1 > m->max_level) m->max_level = l + 1;
+        n_split += count[l];
+        n_label += kids;
+    }
+    m->n_leaves += 7 * n_split;
+    SAL_HIP(hipEventRecord(m->ev[8], s));
+    if (out) {
+        unsigned long long cnt[kNumCounters];
+        SAL_HIP(hipEventSynchronize(m->ev[8]));
+        SAL_HIP(hipMemcpy(cnt, ctx->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+        out->n_leaves = m->n_leaves;
+        out->n_boundary = n_split;
+        out->n_labeled = n_label;
+        out->n_pairs = n_label * set->n_tri;
+        out->n_recheck_pairs = (int64_t)cnt[kCntRecheck];
+        out->ms_mark = elapsed(m->ev[2], m->ev[3]);
+        out->ms_compact = elapsed(m->ev[3], m->ev[4]);
+        out->ms_split = ms_split;
+        out->ms_label = ms_label;
+        out->ms_recheck = ms_recheck;
+        out->ms_total = elapsed(m->ev[2], m->ev[8]);
+        out->graph = 0;
+    }
+    return SAL_OK;
+}
+
+// ----------------------------------------------------- captured round graph
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+uint64_t mixp(uint64_t h, const void *p) { return mix(h, (uint64_t)(uintptr_t)p); }
+
+uint64_t mixd(uint64_t h, double d) {
+    uint64_t u;
+    std::memcpy(&u, &d, sizeof u);
+    return mix(h, u);
+}
+
+int64_t *rs_n(sal::RoundState *rs) {
+    return (int64_t *)((char *)rs + offsetof(sal::RoundState, n));
+}
+
+int64_t *rs_n_kids(sal::RoundState *rs) {
+    return (int64_t *)((char *)rs + offsetof(sal::RoundState, n_kids));
+}
+
+// Grows `cap` to 1.5 budget when fewer than `budget` entries are free, so that
+// a graph captured against these buffers survives the following rounds.
+sal_status reserve_level(sal_tet_mesh *m, int l, int64_t budget, hipStream_t s) {
+    if (m->cap[l] - m->n[l] >= budget) return SAL_OK;
+    return ensure_level(m, l, m->n[l] + budget + budget / 2, s);
+}
+
+// Enqueues the steps of one refine round on q, every size read on the
+// device.  Levels without storage take no part (their split count must be 0,
+// else the plan step stops the round).
+sal_status enqueue_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
+                         const sal_label_options &opt, int64_t kid_cap, hipStream_t q) {
+    RoundState *rs = m->rs;
+    int64_t *n_dev = rs_n(rs);
+    LevelPtrs L = ptrs(m);
+    L.n_dev = n_dev;
+    int64_t off[kMaxLevels + 2] = {0};
+    for (int l = 0; l <= kMaxLevels; ++l) off[l + 1] = off[l] + m->cap[l];
+    SAL_HIP(launch_round_begin(rs, ctx->counters, q));
+    for (int l = 0; l <= kMaxLevels; ++l)
+        if (m->cap[l] > 0) SAL_HIP(launch_clear_flags_dev(m->flag[l], n_dev + l, q));
+    for (int l = 0; l <= kMaxLevels; ++l)
+        if (m->cap[l] > 0) SAL_HIP(launch_mark(L, m->g, m->T, l, q));
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        if (m->cap[l] > 0) {
+            CompactSrc src{m->flag[l], nullptr};
+            SAL_HIP(launch_compact_dev(src, n_dev + l, m->cap[l], m->blocks, m->totals + l,
+                                       m->list + off[l], q));
+        } else {
+            SAL_HIP(launch_fill_u64((unsigned long long *)(m->totals + l), 0ull, 1, q));
+        }
+    }
+    SAL_HIP(launch_plan(rs, m->totals, q));
+    for (int l = kMaxLevels - 1; l >= 0; --l)
+        if (m->cap[l] > 0 && m->cap[l + 1] > 0)
+            SAL_HIP(launch_split_dev(L, m->g, m->T, l, m->list + off[l], m->totals, rs, m->cen[0],
+                                     m->cen[1], m->cen[2], q));
+    sal_status st = enqueue_label_on(ctx, set, kid_cap, rs_n_kids(rs), m->cen[0], m->cen[1],
+                                     m->cen[2], opt, m->lab_scratch, nullptr, nullptr, q);
+    if (st != SAL_OK) return st;
+    for (int l = kMaxLevels - 1; l >= 0; --l)
+        if (m->cap[l] > 0 && m->cap[l + 1] > 0)
+            SAL_HIP(launch_commit(rs, m->totals, l, m->lab_scratch, m->label[l + 1], q));
+    SAL_HIP(launch_round_end(rs, ctx->counters, q));
+    return SAL_OK;
+}
+
+// Runs up to `rounds` rounds as launches of the captured round graph; *done
+// = rounds that completed (the rest stopped for capacity).
+sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
+                        sal_label_options opt, int rounds, sal_refine_stats *out, int *done) {
+    hipStream_t s = ctx->stream;
+    sal_status st;
+    *done = 0;
+    int64_t budget = std::max<int64_t>((int64_t)1 << 20, 2 * m->n_leaves);
+    if (const char *e = std::getenv("SAL_REFINE_GRAPH_BUDGET")) {
+        const long long v = std::atoll(e);
+        if (v > 0) budget = (int64_t)v;
+    }
+    // every level, so that later calls find the same buffers and replay
+    for (int l = 1; l <= kMaxLevels; ++l)
+        if ((st = reserve_level(m, l, budget, s)) != SAL_OK) return st;
+    if (m->cen_cap < budget && (st = ensure_centroids(m, budget + budget / 2, s)) != SAL_OK) return st;
+    if (m->lab_cap < budget &&
+        (st = ensure_buf(&m->lab_scratch, &m->lab_cap, budget + budget / 2, s)) != SAL_OK)
+        return st;
+    if (opt.precision == SAL_PREC_FP32_RECHECK && ctx->flag_cap < budget &&
+        (st = ensure_flag_capacity(ctx, budget + budget / 2)) != SAL_OK)
+        return st;
+    int64_t kid_cap = std::min(m->cen_cap, m->lab_cap);
+    if (opt.precision == SAL_PREC_FP32_RECHECK) kid_cap = std::min(kid_cap, ctx->flag_cap);
+    int64_t list_need = 0, blocks_need = 1;
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        list_need += m->cap[l];
+        blocks_need = std::max<int64_t>(blocks_need, compact_blocks(m->cap[l]) + 1);
+    }
+    if ((st = ensure_buf(&m->list, &m->list_cap, list_need, s)) != SAL_OK) return st;
+    if ((st = ensure_buf(&m->blocks, &m->blocks_cap, blocks_need, s)) != SAL_OK) return st;
+    if (!m->rs && hipMalloc((void **)&m->rs, sizeof(RoundState)) != hipSuccess)
+        return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(round state)");
+
+    // The launch shape is fixed in the graph: resolve it now (tuning
+    // synchronises), on lattice centroids written into the scratch.
+    if (opt.points_per_lane == 0 || opt.block_waves == 0) {
+        const int64_t nt = std::min<int64_t>(std::min<int64_t>(m->n[0], kid_cap), (int64_t)1 << 19);
+        SAL_HIP(launch_lattice_centroids(m->g, nt, m->cen[0], m->cen[1], m->cen[2], s));
+        if ((st = tune_launch(ctx, set, kid_cap, m->cen[0], m->cen[1], m->cen[2], m->lab_scratch,
+                              &opt)) != SAL_OK)
+            return st;
+    }
+
+    uint64_t key = mix(0x5a1d5a1dull, set->uid);
+    key = mixp(key, ctx);
+    key = mixp(key, ctx->flag_list);
+    key = mixp(key, ctx->counters);
+    key = mix(key, (uint64_t)opt.precision);
+    key = mixd(key, opt.threshold);
+    key = mixd(key, opt.recheck_band);
+    key = mixd(key, opt.kappa);
+    key = mix(key, (uint64_t)opt.points_per_lane);
+    key = mix(key, (uint64_t)opt.block_waves);
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        key = mixp(key, m->key[l]);
+        key = mixp(key, m->label[l]);
+        key = mixp(key, m->child[l]);
+        key = mixp(key, m->flag[l]);
+        key = mix(key, (uint64_t)m->cap[l]);
+    }
+    for (auto *c : m->cen) key = mixp(key, c);
+    key = mixp(key, m->lab_scratch);
+    key = mixp(key, m->list);
+    key = mixp(key, m->blocks);
+    key = mixp(key, m->totals);
+    key = mixp(key, m->rs);
+    key = mix(key, (uint64_t)kid_cap);
+    const bool capture = !m->round_graph || m->round_key != key;
+    if (capture) {
+        if (m->round_graph) {
+            SAL_HIP(hipGraphExecDestroy(m->round_graph));
+            m->round_graph = nullptr;
+        }
+        m->round_key = 0;
+        SAL_HIP(hipStreamSynchronize(s));
+        hipGraph_t g = nullptr;
+        SAL_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        sal_status cst = enqueue_round(ctx, m, set, opt, kid_cap, ctx->capture_stream);
+        hipError_t ee = hipStreamEndCapture(ctx->capture_stream, &g);
+        if (cst != SAL_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cst;
+        }
+        if (ee != hipSuccess) return hip_error(ee, "hipStreamEndCapture");
+        ee = hipGraphInstantiate(&m->round_graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ee != hipSuccess) return hip_error(ee, "hipGraphInstantiate");
+        m->round_key = key;
+    }
+
+    RoundState h{};
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        h.n[l] = m->n[l];
+        h.cap[l] = m->cap[l];
+    }
+    h.kid_cap = kid_cap;
+    h.n_leaves = m->n_leaves;
+    SAL_HIP(hipStreamSynchronize(s));
+    SAL_HIP(hipMemcpy(m->rs, &h, sizeof h, hipMemcpyHostToDevice));
+    SAL_HIP(hipEventRecord(m->ev[11], s));
+    for (int r = 0; r < rounds; ++r) {
+        SAL_HIP(hipGraphLaunch(m->round_graph, s));
+        SAL_HIP(hipEventRecord(m->ev[12 + r], s));
+    }
+    SAL_HIP(hipStreamSynchronize(s));
+    SAL_HIP(hipMemcpy(&h, m->rs, sizeof h, hipMemcpyDeviceToHost));
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        m->n[l] = h.n[l];
+        if (h.n[l] > 0 && l > m->max_level) m->max_level = l;
+    }
+    m->n_leaves = h.n_leaves;
+    *done = h.round;
+    if (out) {
+        for (int r = 0; r < h.round; ++r) {
+            sal_refine_stats &o = out[r];
+            o.n_leaves = h.stat[r].n_leaves;
+            o.n_boundary = h.stat[r].n_boundary;
+            o.n_labeled = h.stat[r].n_labeled;
+            o.n_pairs = h.stat[r].n_labeled * set->n_tri;
+            o.n_recheck_pairs = h.stat[r].n_recheck_pairs;
+            o.ms_total = elapsed(m->ev[11 + r], m->ev[12 + r]);
+            o.graph = capture ? 1 : 2;
+        }
+    }
+    if (h.status == 2) return set_error(SAL_ERR_CAPACITY, "refinement beyond level 3");
+    return SAL_OK;
 }
 
 }  // namespace
@@ -177,6 +465,9 @@ void sal_tet_mesh_destroy(sal_tet_mesh *m) {
     if (m->list) (void)hipFree(m->list);
     if (m->blocks) (void)hipFree(m->blocks);
     if (m->totals) (void)hipFree(m->totals);
+    if (m->lab_scratch) (void)hipFree(m->lab_scratch);
+    if (m->rs) (void)hipFree(m->rs);
+    if (m->round_graph) (void)hipGraphExecDestroy(m->round_graph);
     for (auto &e : m->ev)
         if (e) (void)hipEventDestroy(e);
     delete m;
@@ -258,11 +549,13 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
         if (!m->labeled0) {
             if ((st = ensure_centroids(m, m->n[0], s)) != SAL_OK) return st;
             SAL_HIP(launch_lattice_centroids(m->g, m->n[0], m->cen[0], m->cen[1], m->cen[2], s));
-            if ((st = label_scratch(ctx, m, set, m->n[0], opt, m->label[0], m->ev[9])) != SAL_OK)
+            if ((st = label_scratch(ctx, m, set, m->n[0], opt, m->label[0], m->ev[10],
+                                    m->ev[9])) != SAL_OK)
                 return st;
             m->labeled0 = true;
             labeled0 = m->n[0];
         } else {
+            SAL_HIP(hipEventRecord(m->ev[10], s));
             SAL_HIP(hipEventRecord(m->ev[9], s));
         }
         SAL_HIP(hipEventRecord(m->ev[1], s));
@@ -274,83 +567,21 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
             r0.n_labeled = labeled0;
             r0.n_pairs = labeled0 * set->n_tri;
             r0.n_recheck_pairs = (int64_t)cnt[kCntRecheck];
-            r0.ms_label = elapsed(m->ev[0], m->ev[9]);
+            r0.ms_label = elapsed(m->ev[10], m->ev[9]);
             r0.ms_recheck = elapsed(m->ev[9], m->ev[1]);
             r0.ms_total = elapsed(m->ev[0], m->ev[1]);
         }
 
-        for (int r = 1; r <= rounds; ++r) {
-            const int top = m->max_level;
-            int64_t total_entries = 0;
-            for (int l = 0; l <= top; ++l) total_entries += m->n[l];
-            if ((st = ensure_buf(&m->list, &m->list_cap, total_entries, s)) != SAL_OK) return st;
-            SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, s));
-            SAL_HIP(hipEventRecord(m->ev[2], s));
-            for (int l = 0; l <= top; ++l) SAL_HIP(launch_fill_u8(m->flag[l], 0, m->n[l], s));
-            LevelPtrs L = ptrs(m);
-            for (int l = 0; l <= top; ++l) SAL_HIP(launch_mark(L, m->g, m->T, l, s));
-            SAL_HIP(hipEventRecord(m->ev[3], s));
-            int64_t off[kMaxLevels + 2] = {0};
-            for (int l = 0; l <= top; ++l) {
-                off[l + 1] = off[l] + m->n[l];
-                CompactSrc src{m->flag[l], nullptr};
-                if ((st = compact(m, src, m->n[l], m->list + off[l], m->totals + l, s)) != SAL_OK)
-                    return st;
-            }
-            SAL_HIP(hipEventRecord(m->ev[4], s));
-            int64_t count[kMaxLevels + 1] = {0};
-            SAL_HIP(hipMemcpyAsync(count, m->totals, sizeof(int64_t) * (top + 1),
-                                   hipMemcpyDeviceToHost, s));
-            SAL_HIP(hipStreamSynchronize(s));
-            if (top == kMaxLevels && count[top] > 0)
-                return set_error(SAL_ERR_CAPACITY, "refinement beyond level 3");
-            int64_t n_split = 0, n_label = 0;
-            float ms_split = 0.0f, ms_label = 0.0f, ms_recheck = 0.0f;
-            // deepest level first: its children array never moves under a
-            // pending split of a coarser level
-            for (int l = top; l >= 0; --l) {
-                if (count[l] == 0) continue;
-                const int64_t kids = 8 * count[l];
-                if ((st = ensure_level(m, l + 1, m->n[l + 1] + kids, s)) != SAL_OK) return st;
-                if ((st = ensure_centroids(m, kids, s)) != SAL_OK) return st;
-                const int64_t base_block = m->n[l + 1] / 8;
-                LevelPtrs L2 = ptrs(m);
-                SAL_HIP(hipEventRecord(m->ev[5], s));
-                SAL_HIP(launch_split(L2, m->g, m->T, l, m->list + off[l], count[l], base_block,
-                                     m->cen[0], m->cen[1], m->cen[2], s));
-                SAL_HIP(hipEventRecord(m->ev[6], s));
-                m->n[l + 1] += kids;
-                if ((st = label_scratch(ctx, m, set, kids, opt, m->label[l + 1] + 8 * base_block,
-                                        m->ev[9])) != SAL_OK)
-                    return st;
-                SAL_HIP(hipEventRecord(m->ev[7], s));
-                SAL_HIP(hipEventSynchronize(m->ev[7]));
-                ms_split += elapsed(m->ev[5], m->ev[6]);
-                ms_label += elapsed(m->ev[6], m->ev[9]);
-                ms_recheck += elapsed(m->ev[9], m->ev[7]);
-                if (l + 1 > m->max_level) m->max_level = l + 1;
-                n_split += count[l];
-                n_label += kids;
-            }
-            m->n_leaves += 7 * n_split;
-            SAL_HIP(hipEventRecord(m->ev[8], s));
-            if (per_round) {
-                SAL_HIP(hipEventSynchronize(m->ev[8]));
-                SAL_HIP(hipMemcpy(cnt, ctx->counters, sizeof(cnt), hipMemcpyDeviceToHost));
-                sal_refine_stats &rs = per_round[r];
-                rs.n_leaves = m->n_leaves;
-                rs.n_boundary = n_split;
-                rs.n_labeled = n_label;
-                rs.n_pairs = n_label * set->n_tri;
-                rs.n_recheck_pairs = (int64_t)cnt[kCntRecheck];
-                rs.ms_mark = elapsed(m->ev[2], m->ev[3]);
-                rs.ms_compact = elapsed(m->ev[3], m->ev[4]);
-                rs.ms_split = ms_split;
-                rs.ms_label = ms_label;
-                rs.ms_recheck = ms_recheck;
-                rs.ms_total = elapsed(m->ev[2], m->ev[8]);
-            }
+        int first = 1;
+        if (opt.use_graph && rounds > 0) {
+            int done = 0;
+            st = graph_rounds(ctx, m, set, opt, rounds, per_round ? per_round + 1 : nullptr, &done);
+            if (st != SAL_OK) return st;
+            first = 1 + done;
         }
+        for (int r = first; r <= rounds; ++r)
+            if ((st = eager_round(ctx, m, set, opt, per_round ? per_round + r : nullptr)) != SAL_OK)
+                return st;
         return SAL_OK;
     } catch (...) {
         return set_error(SAL_ERR_INTERNAL, "exception in sal_refine_relabel");

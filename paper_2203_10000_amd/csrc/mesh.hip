@@ -131,9 +131,12 @@ __device__ __forceinline__ void resolve(const LevelPtrs &L, const LatticeGeom &g
 // its four faces at the same level; when the other side is a leaf (or lies in
 // a coarser leaf) with another label, both are flagged.  When the other side
 // is finer, its leaves find this one the same way, so every pair is seen.
-__global__ void k_mark(LevelPtrs L, LatticeGeom g, ChildTables T, int l) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L.n[l]) return;
+__device__ __forceinline__ int64_t level_n(const LevelPtrs &L, int l) {
+    return L.n_dev ? L.n_dev[l] : L.n[l];
+}
+
+__device__ void mark_one(const LevelPtrs &L, const LatticeGeom &g, const ChildTables &T, int l,
+                         int64_t i) {
     if (L.child[l][i] >= 0) return;
     const int32_t lab = L.label[l][i];
     int q, lk;
@@ -166,6 +169,13 @@ __global__ void k_mark(LevelPtrs L, LatticeGeom g, ChildTables T, int l) {
     if (mine) L.flag[l][i] = 1;
 }
 
+__global__ void k_mark(LevelPtrs L, LatticeGeom g, ChildTables T, int l) {
+    const int64_t n = level_n(L, l);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        mark_one(L, g, T, l, i);
+}
+
 // ------------------------------------------------------------- compaction
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
@@ -176,8 +186,10 @@ __device__ __forceinline__ bool pred(const CompactSrc &s, int64_t i) {
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_count(CompactSrc s, int64_t n,
+                                                        const int64_t *__restrict__ n_dev,
                                                         int64_t *__restrict__ block_counts) {
     __shared__ int red[kScanThreads];
+    if (n_dev) n = *n_dev;
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     int cnt = 0;
     for (int r = 0; r < kScanItems; ++r) {
@@ -220,9 +232,11 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int64_t *__restrict__ coun
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scatter(CompactSrc s, int64_t n,
+                                                          const int64_t *__restrict__ n_dev,
                                                           const int64_t *__restrict__ offsets,
                                                           int32_t *__restrict__ out) {
     __shared__ int part[kScanThreads];
+    if (n_dev) n = *n_dev;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int cnt = 0;
     for (int r = 0; r < kScanItems; ++r) {
@@ -246,12 +260,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter(CompactSrc s, int64_t 
 
 // Section 2.1.2: each listed leaf of level l becomes 8 level-(l+1) tetrahedra
 // (red refinement); they are appended as one block, their centroids written
-// to the labeling scratch.
-__global__ void k_split(LevelPtrs L, LatticeGeom g, ChildTables T, int l,
-                        const int32_t *__restrict__ list, int64_t count, int64_t base_block,
-                        float *__restrict__ cx, float *__restrict__ cy, float *__restrict__ cz) {
-    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (jj >= count * 8) return;
+// to the labeling scratch.  jj = 8 (list position) + child rank.
+__device__ void split_one(const LevelPtrs &L, const LatticeGeom &g, const ChildTables &T, int l,
+                          const int32_t *__restrict__ list, int64_t jj, int64_t base_block,
+                          float *__restrict__ cx, float *__restrict__ cy, float *__restrict__ cz) {
     const int64_t j = jj >> 3;
     const int r = (int)(jj & 7);
     const int64_t i = list[j];
@@ -269,6 +281,97 @@ __global__ void k_split(LevelPtrs L, LatticeGeom g, ChildTables T, int l,
     L.child[l + 1][o] = -1;
     L.label[l + 1][o] = -2;
     centroid(g, l + 1, cq, cc, cx[jj], cy[jj], cz[jj]);
+}
+
+__global__ void k_split(LevelPtrs L, LatticeGeom g, ChildTables T, int l,
+                        const int32_t *__restrict__ list, int64_t count, int64_t base_block,
+                        float *__restrict__ cx, float *__restrict__ cy, float *__restrict__ cz) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= count * 8) return;
+    split_one(L, g, T, l, list, jj, base_block, cx, cy, cz);
+}
+
+// ------------------------------------------------- captured refine round
+// These kernels take every size from RoundState or the compaction totals, so
+// the same launch sequence serves every round; fixed grids stride over them.
+constexpr int kDevGrid = 2048;
+
+__global__ void k_round_begin(RoundState *rs, unsigned long long *counters) {
+    const int t = threadIdx.x;
+    if (t < kNumCounters) counters[t] = 0ull;
+    if (t == 0) rs->n_kids = 0;
+}
+
+__global__ void k_clear_flags_dev(uint8_t *__restrict__ flag, const int64_t *__restrict__ n_dev) {
+    const int64_t n = *n_dev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) flag[i] = 0;
+}
+
+// One thread: sizes of this round's splits (levels deepest first, as the
+// host-driven round orders them), capacity checks, new level sizes.
+__global__ void k_plan(RoundState *rs, const int64_t *__restrict__ totals) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    rs->n_kids = 0;
+    if (rs->status) return;
+    if (rs->round > kMaxLevels) { rs->status = 2; return; }
+    int64_t cnt[kMaxLevels + 1];
+    int64_t boundary = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        cnt[l] = totals[l];
+        boundary += cnt[l];
+    }
+    if (cnt[kMaxLevels] > 0) { rs->status = 2; return; }
+    int64_t run = 0;
+    for (int l = kMaxLevels - 1; l >= 0; --l) {
+        if (rs->n[l + 1] + 8 * cnt[l] > rs->cap[l + 1]) { rs->status = 1; return; }
+        rs->kid_off[l] = run;
+        run += 8 * cnt[l];
+    }
+    if (run > rs->kid_cap) { rs->status = 1; return; }
+    for (int l = kMaxLevels - 1; l >= 0; --l) {
+        rs->base_block[l] = rs->n[l + 1] / 8;
+        rs->n[l + 1] += 8 * cnt[l];
+    }
+    rs->n_kids = run;
+    rs->n_leaves += 7 * boundary;
+    RoundStat &st = rs->stat[rs->round];
+    st.n_leaves = rs->n_leaves;
+    st.n_boundary = boundary;
+    st.n_labeled = run;
+}
+
+__global__ void k_split_dev(LevelPtrs L, LatticeGeom g, ChildTables T, int l,
+                            const int32_t *__restrict__ list, const int64_t *__restrict__ totals,
+                            const RoundState *__restrict__ rs, float *__restrict__ cx,
+                            float *__restrict__ cy, float *__restrict__ cz) {
+    if (rs->status) return;
+    const int64_t n = 8 * totals[l];
+    const int64_t base_block = rs->base_block[l];
+    const int64_t off = rs->kid_off[l];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; jj < n; jj += stride)
+        split_one(L, g, T, l, list, jj, base_block, cx + off, cy + off, cz + off);
+}
+
+// Copies the children's labels from the labeling scratch into level l + 1.
+__global__ void k_commit(const RoundState *__restrict__ rs, const int64_t *__restrict__ totals,
+                         int l, const int32_t *__restrict__ scratch_labels,
+                         int32_t *__restrict__ level_labels) {
+    if (rs->status) return;
+    const int64_t n = 8 * totals[l];
+    const int32_t *src = scratch_labels + rs->kid_off[l];
+    int32_t *dst = level_labels + 8 * rs->base_block[l];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+        dst[j] = src[j];
+}
+
+__global__ void k_round_end(RoundState *rs, const unsigned long long *__restrict__ counters) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (rs->status) return;
+    rs->stat[rs->round].n_recheck_pairs = (int64_t)counters[kCntRecheck];
+    rs->round += 1;
 }
 
 __global__ void k_export(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
@@ -317,6 +420,10 @@ hipError_t launch_lattice_centroids(const LatticeGeom &g, int64_t n0, float *cx,
 
 hipError_t launch_mark(const LevelPtrs &L, const LatticeGeom &g, const ChildTables &T, int l,
                        hipStream_t s) {
+    if (L.n_dev) {
+        k_mark<<<kDevGrid, 256, 0, s>>>(L, g, T, l);
+        return hipGetLastError();
+    }
     if (L.n[l] <= 0) return hipSuccess;
     k_mark<<<grid_for(L.n[l], 256), 256, 0, s>>>(L, g, T, l);
     return hipGetLastError();
@@ -328,9 +435,53 @@ hipError_t launch_compact(const CompactSrc &src, int64_t n, int64_t *block_scrat
                           int64_t *total, int32_t *out, hipStream_t s) {
     const int64_t nb = compact_blocks(n);
     if (nb <= 0) return launch_fill_u64((unsigned long long *)total, 0ull, 1, s);
-    k_count<<<(unsigned)nb, kScanThreads, 0, s>>>(src, n, block_scratch);
+    k_count<<<(unsigned)nb, kScanThreads, 0, s>>>(src, n, nullptr, block_scratch);
     k_scan_blocks<<<1, 1024, 0, s>>>(block_scratch, nb, total);
-    k_scatter<<<(unsigned)nb, kScanThreads, 0, s>>>(src, n, block_scratch, out);
+    k_scatter<<<(unsigned)nb, kScanThreads, 0, s>>>(src, n, nullptr, block_scratch, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_begin(RoundState *rs, unsigned long long *counters, hipStream_t s) {
+    k_round_begin<<<1, 64, 0, s>>>(rs, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flags_dev(uint8_t *flag, const int64_t *n_dev, hipStream_t s) {
+    k_clear_flags_dev<<<kDevGrid, 256, 0, s>>>(flag, n_dev);
+    return hipGetLastError();
+}
+
+// Tiles for `cap` entries; tiles past the device-side size count nothing.
+hipError_t launch_compact_dev(const CompactSrc &src, const int64_t *n_dev, int64_t cap,
+                              int64_t *block_scratch, int64_t *total, int32_t *out, hipStream_t s) {
+    const int64_t nb = compact_blocks(cap);
+    if (nb <= 0) return launch_fill_u64((unsigned long long *)total, 0ull, 1, s);
+    k_count<<<(unsigned)nb, kScanThreads, 0, s>>>(src, cap, n_dev, block_scratch);
+    k_scan_blocks<<<1, 1024, 0, s>>>(block_scratch, nb, total);
+    k_scatter<<<(unsigned)nb, kScanThreads, 0, s>>>(src, cap, n_dev, block_scratch, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(RoundState *rs, const int64_t *totals, hipStream_t s) {
+    k_plan<<<1, 64, 0, s>>>(rs, totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_dev(const LevelPtrs &L, const LatticeGeom &g, const ChildTables &T, int l,
+                            const int32_t *list, const int64_t *totals, const RoundState *rs,
+                            float *cx, float *cy, float *cz, hipStream_t s) {
+    k_split_dev<<<kDevGrid, 256, 0, s>>>(L, g, T, l, list, totals, rs, cx, cy, cz);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(const RoundState *rs, const int64_t *totals, int l,
+                         const int32_t *scratch_labels, int32_t *level_labels, hipStream_t s) {
+    k_commit<<<kDevGrid, 256, 0, s>>>(rs, totals, l, scratch_labels, level_labels);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_end(RoundState *rs, const unsigned long long *counters, hipStream_t s) {
+    k_round_end<<<1, 64, 0, s>>>(rs, counters);
     return hipGetLastError();
 }
 

@@ -18,6 +18,29 @@ struct LevelPtrs {
     int32_t *child[kMaxLevels + 1];
     uint8_t *flag[kMaxLevels + 1];
     int64_t n[kMaxLevels + 1];
+    const int64_t *n_dev;   // device copy of the level sizes; when set it replaces n
+};
+
+// Per-round figures kept on the device by the captured refine round.
+struct RoundStat {
+    int64_t n_leaves, n_boundary, n_labeled, n_recheck_pairs;
+};
+
+// Device-resident state of the captured refine round: every size the round
+// needs lives here, so one captured graph serves every round.  The plan step
+// turns `status` nonzero (sticky) instead of writing past a capacity; the
+// steps that change the mesh then do nothing.
+struct RoundState {
+    int64_t n[kMaxLevels + 1];           // entries per level
+    int64_t cap[kMaxLevels + 1];         // capacity per level
+    int64_t base_block[kMaxLevels + 1];  // first child block of each level's splits
+    int64_t kid_off[kMaxLevels + 1];     // each level's children in the labeling scratch
+    int64_t n_kids;                      // children made this round
+    int64_t kid_cap;                     // labeling scratch capacity
+    int64_t n_leaves;
+    int32_t status;                      // 0 ok, 1 out of capacity, 2 beyond the deepest level
+    int32_t round;                       // rounds completed
+    RoundStat stat[kMaxLevels + 1];
 };
 
 struct LatticeGeom {
@@ -52,6 +75,20 @@ hipError_t launch_split(const LevelPtrs &L, const LatticeGeom &g, const ChildTab
 hipError_t launch_export(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
                          int64_t count, int64_t out_base, uint64_t *keys, int32_t *labels,
                          float *cx, float *cy, float *cz, hipStream_t s);
+// Device-sized forms for the captured refine round (sizes read from
+// RoundState / compaction totals; fixed grids stride over them).
+hipError_t launch_round_begin(RoundState *rs, unsigned long long *counters, hipStream_t s);
+hipError_t launch_clear_flags_dev(uint8_t *flag, const int64_t *n_dev, hipStream_t s);
+hipError_t launch_compact_dev(const CompactSrc &src, const int64_t *n_dev, int64_t cap,
+                              int64_t *block_scratch, int64_t *total, int32_t *out, hipStream_t s);
+hipError_t launch_plan(RoundState *rs, const int64_t *totals, hipStream_t s);
+hipError_t launch_split_dev(const LevelPtrs &L, const LatticeGeom &g, const ChildTables &T, int l,
+                            const int32_t *list, const int64_t *totals, const RoundState *rs,
+                            float *cx, float *cy, float *cz, hipStream_t s);
+hipError_t launch_commit(const RoundState *rs, const int64_t *totals, int l,
+                         const int32_t *scratch_labels, int32_t *level_labels, hipStream_t s);
+hipError_t launch_round_end(RoundState *rs, const unsigned long long *counters, hipStream_t s);
+
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 

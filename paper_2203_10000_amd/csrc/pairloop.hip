@@ -23,6 +23,8 @@ using namespace f32;
 template <int P>
 __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
     const int64_t blk = (int64_t)blockIdx.x * blockDim.x * P;
+    const int64_t n = a.n_dev ? *a.n_dev : a.n;
+    if (blk >= n) return;   // whole workgroup past the end (grid sized for a capacity)
     const CRec32 *rec = (const CRec32 *)a.rec32;
     const CSurf *surf = (const CSurf *)a.surf;
     float px[P], py[P], pz[P];
@@ -32,7 +34,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         idx[j] = blk + (int64_t)j * blockDim.x + threadIdx.x;
-        valid[j] = idx[j] < a.n;
+        valid[j] = idx[j] < n;
         px[j] = valid[j] ? a.x[idx[j]] : 0.0f;
         py[j] = valid[j] ? a.y[idx[j]] : 0.0f;
         pz[j] = valid[j] ? a.z[idx[j]] : 0.0f;
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
             if (band || cond) flg[j] |= 1ull << k;
             if (in) { enc[j] |= 1ull << k; lab[j] = slabel; }
             if (a.winding && valid[j]) {
-                const int64_t o = (int64_t)k * a.n + idx[j];
+                const int64_t o = (int64_t)k * n + idx[j];
                 const double wv = good[j] ? w : __builtin_nan("");
                 if (a.winding_type == SAL_WINDING_F64) ((double *)a.winding)[o] = wv;
                 else ((float *)a.winding)[o] = (float)wv;
@@ -96,7 +98,9 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
 // exact-sign guard; labels are final.
 __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < a.n;
+    const int64_t n = a.n_dev ? *a.n_dev : a.n;
+    if ((int64_t)blockIdx.x * blockDim.x >= n) return;
+    const bool valid = i < n;
     float fx = valid ? a.x[i] : 0.0f, fy = valid ? a.y[i] : 0.0f, fz = valid ? a.z[i] : 0.0f;
     const bool good = valid && finite3(fx, fy, fz);
     if (!good) { fx = 0.0f; fy = 0.0f; fz = 0.0f; }
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
         const double w = S * kInv2Pi;
         if (on || w >= a.threshold) lab = surf[k].label;
         if (a.winding && valid) {
-            const int64_t o = (int64_t)k * a.n + i;
+            const int64_t o = (int64_t)k * n + i;
             const double wv = good ? w : __builtin_nan("");
             if (a.winding_type == SAL_WINDING_F64) ((double *)a.winding)[o] = wv;
             else ((float *)a.winding)[o] = (float)wv;

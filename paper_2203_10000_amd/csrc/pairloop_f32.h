@@ -70,19 +70,37 @@ struct Vtx {
     float x, y, z, r;   // vertex - p and its length
 };
 
+// The eight floats of one triangle record, held in SGPRs.
+struct TriRec {
+    float v[8];
+};
+
+// The load is volatile only to pin it where the source puts it: the compiler
+// would otherwise sink a prefetch down to the end of the loop body, next to
+// the copy that consumes it.  It is still one scalar load.
+__device__ __forceinline__ TriRec load_rec(const CRec32 *p) {
+    typedef float F8 __attribute__((ext_vector_type(8)));
+    typedef __attribute__((address_space(4))) const volatile F8 VF8;
+    const F8 w = *(const VF8 *)p;
+    TriRec r;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) r.v[c] = w[c];
+    return r;
+}
+
 // One strip step for P points: the triangle (O, N, Z) with Z and its normal in
 // record `rec`.  Z is written to the free slot F; the caller rotates the three
 // slots (O, N, F) -> (N, F, O) instead of moving registers.
 template <int P>
 __device__ __forceinline__ void f32_step(const Vtx (&O)[P], const Vtx (&N)[P], Vtx (&F)[P],
-                                         float (&e01)[P],
-                                         float (&rr01)[P], float (&acc)[P], const CRec32 *rec,
-                                         const float (&px)[P], const float (&py)[P],
-                                         const float (&pz)[P], const uint64_t (&good_mask)[P], float kap,
+                                         float (&e01)[P], float (&rr01)[P], float (&acc)[P],
+                                         const TriRec &rec, const float (&px)[P],
+                                         const float (&py)[P], const float (&pz)[P],
+                                         const uint64_t (&good_mask)[P], float kap,
                                          float branch_cut, uint64_t (&cmask)[P]) {
-    const float q0 = rec->v[0], q1 = rec->v[1], q2 = rec->v[2];
-    const float q3 = rec->v[3], q4 = rec->v[4], q5 = rec->v[5];
-    const float q6 = rec->v[6], q7 = rec->v[7];
+    const float q0 = rec.v[0], q1 = rec.v[1], q2 = rec.v[2];
+    const float q3 = rec.v[3], q4 = rec.v[4], q5 = rec.v[5];
+    const float q6 = rec.v[6], q7 = rec.v[7];
     float x2[P], y2[P], z2[P], r2[P], e02[P], e12[P], nn[P], mm[P], dd[P];
     uint64_t near = 0;
 #pragma unroll
@@ -158,17 +176,37 @@ __device__ __forceinline__ void surface_sum(const CRec32 *rec, int64_t rec_begin
             rr01[j] = A[j].r * B[j].r;
             acc[j] = 0.0f;
         }
+        // Triangle records are prefetched one step ahead: each step first
+        // waits for the scalar loads in flight (the record it is about to
+        // use), then issues the load of the next record, then computes, so a
+        // load overlaps a whole step.  The explicit wait orders the two
+        // (scalar loads can return out of order, so any wait is a wait for
+        // all of them).  Indices are clamped to the strip's last record.
         const CRec32 *tr = h + 1;
+        const int last = m - 1;
+        TriRec c0 = load_rec(tr), c1, c2;
         int t = 0;
         for (; t + 2 < m; t += 3) {
-            f32_step<P>(A, B, C, e01, rr01, acc, tr + t, px, py, pz, good_mask, kap, branch_cut, cmask);
-            f32_step<P>(B, C, A, e01, rr01, acc, tr + t + 1, px, py, pz, good_mask, kap, branch_cut, cmask);
-            f32_step<P>(C, A, B, e01, rr01, acc, tr + t + 2, px, py, pz, good_mask, kap, branch_cut, cmask);
+            __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+            c1 = load_rec(tr + (t + 1));
+            __builtin_amdgcn_sched_barrier(0);     // keep the step's arithmetic below
+            f32_step<P>(A, B, C, e01, rr01, acc, c0, px, py, pz, good_mask, kap, branch_cut, cmask);
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            c2 = load_rec(tr + (t + 2));
+            __builtin_amdgcn_sched_barrier(0);
+            f32_step<P>(B, C, A, e01, rr01, acc, c1, px, py, pz, good_mask, kap, branch_cut, cmask);
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            c0 = load_rec(tr + (t + 3 < last ? t + 3 : last));
+            __builtin_amdgcn_sched_barrier(0);
+            f32_step<P>(C, A, B, e01, rr01, acc, c2, px, py, pz, good_mask, kap, branch_cut, cmask);
         }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
         if (t < m) {
-            f32_step<P>(A, B, C, e01, rr01, acc, tr + t, px, py, pz, good_mask, kap, branch_cut, cmask);
-            if (t + 1 < m)
-                f32_step<P>(B, C, A, e01, rr01, acc, tr + t + 1, px, py, pz, good_mask, kap, branch_cut, cmask);
+            f32_step<P>(A, B, C, e01, rr01, acc, c0, px, py, pz, good_mask, kap, branch_cut, cmask);
+            if (t + 1 < m) {
+                c1 = load_rec(tr + (t + 1));
+                f32_step<P>(B, C, A, e01, rr01, acc, c1, px, py, pz, good_mask, kap, branch_cut, cmask);
+            }
         }
 #pragma unroll
         for (int j = 0; j < P; ++j) S[j] += (double)acc[j];

@@ -39,7 +39,8 @@ struct sal_surface_set {
     int64_t n_tri = 0, n_strips = 0, n_rec = 0, bytes = 0;
     sal::Rec32 *rec32 = nullptr;
     sal::Rec64 *rec64 = nullptr;
-    sal::SurfaceDev *surf = nullptr;
+    sal::SurfaceDev *surf = nullptr;        // n_surf entries, then the two tuner entries
+    sal::SurfaceDev *tune_surf = nullptr;   // surf + n_surf: [0] float32 trials, [1] FP64 trials
     int64_t *strip_off = nullptr;
     std::vector<sal::SurfaceDev> host_table;
     std::vector<int64_t> host_strip_off;   // record index of every strip head
@@ -59,15 +60,27 @@ sal_status ensure_flag_capacity(sal_context *ctx, int64_t n);
 sal_status resolve_options(const sal_label_options *in, sal_label_options *out);
 
 // Enqueues one labeling pass (pair loop, and recheck in the float32 form) of
-// n points; counters must be cleared by the caller.  Records events ev_a
-// (after the pair loop) when non-null.
+// n points; counters must be cleared by the caller.  The launch shape is
+// resolved first (tune_launch); then ev_start (before the pair loop) and
+// ev_after_pairloop are recorded when non-null, so that timings bracketed by
+// them leave out any tuning.
 sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
                          const float *y, const float *z, const sal_label_options &opt,
-                         int32_t *labels, void *winding, hipEvent_t ev_after_pairloop,
-                         int *shape = nullptr);
+                         int32_t *labels, void *winding, hipEvent_t ev_start,
+                         hipEvent_t ev_after_pairloop, int *shape = nullptr);
+
+// The launches of one labeling pass with a resolved launch shape, on
+// `stream`.  With n_dev set the point count is read on the device and n is the
+// capacity the grids are sized for (the form a captured graph uses).
+sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_t n,
+                            const int64_t *n_dev, const float *x, const float *y, const float *z,
+                            const sal_label_options &opt, int32_t *labels, void *winding,
+                            hipEvent_t ev_mid, hipStream_t stream);
 
 // Resolves points_per_lane / block_waves left at 0 by timing the candidates
-// (first use of a size bucket synchronises the stream), cached per process.
+// on a prefix of the points against a prefix of the strips (the tuner table
+// entries), so a trial costs a bounded number of pairs; the first use of a
+// size bucket synchronises the stream.  Cached per process.
 sal_status tune_launch(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
                        const float *y, const float *z, int32_t *labels, sal_label_options *opt);
 

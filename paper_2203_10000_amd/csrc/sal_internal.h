@@ -46,6 +46,9 @@ constexpr float kKnSmall = 5.0f;     // small-angle path needs D > 5 |n| r_Z + .
 constexpr int kMaxSurfaces = 64;     // per-point masks are 64-bit
 
 // Per-surface table in device memory.
+// Triangles per tuner trial launch: float32 form, FP64 form.
+constexpr int64_t kTuneTri[2] = {32768, 8192};
+
 struct SurfaceDev {
     int64_t rec_begin, rec_end;      // [begin, end) in both record streams
     int64_t strip_begin, strip_end;  // [begin, end) in the strip table
@@ -81,6 +84,8 @@ struct PairloopArgs {
     const float *__restrict__ y;
     const float *__restrict__ z;
     int64_t n;
+    const int64_t *__restrict__ n_dev;   // when set, the point count is read here (n is the
+                                         // capacity the grid was sized for)
     float kappa;
     double threshold;
     double band;

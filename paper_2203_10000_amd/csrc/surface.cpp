@@ -252,6 +252,22 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
         sd.strip_end = (int64_t)strip_off.size();
     }
 
+    // Two extra table entries for the launch-shape tuner: the leading whole
+    // strips of the record stream up to about kTuneTri[i] triangles, so that
+    // a trial launch costs a bounded number of pairs on any mesh.
+    for (int i = 0; i < 2; ++i) {
+        SurfaceDev t{};
+        int64_t s = 0, tris = 0;
+        while (s < (int64_t)strip_off.size() && tris < kTuneTri[i]) tris += strip_tris[(size_t)s++];
+        t.rec_begin = 0;
+        t.rec_end = s < (int64_t)strip_off.size() ? strip_off[(size_t)s] : (int64_t)r32.size();
+        t.strip_begin = 0;
+        t.strip_end = s;
+        t.n_tri = tris;
+        t.label = 1;
+        table.push_back(t);
+    }
+
     SAL_HIP(hipSetDevice(ctx->device));
     static std::atomic<uint64_t> next_uid{1};
     auto *set = new sal_surface_set();
@@ -261,7 +277,7 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
     set->n_tri = total_tri;
     set->n_strips = (int64_t)strip_off.size();
     set->n_rec = (int64_t)r32.size();
-    set->host_table = table;
+    set->host_table.assign(table.begin(), table.begin() + n);
     set->host_strip_off = strip_off;
     set->host_strip_tris = strip_tris;
     sal_status st = SAL_OK;
@@ -281,6 +297,7 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
         destroy_surface_set(set);
         return st;
     }
+    set->tune_surf = set->surf + n;
     *out = set;
     return SAL_OK;
 }

@@ -91,14 +91,14 @@ sal_status tune_launch(sal_context *ctx, const sal_surface_set *set, int64_t n, 
         }
     }
     // Trial launches of the pair loop alone on a prefix of the points (enough
-    // workgroups to fill the device several times), writing labels that the
-    // real launch overwrites.
+    // workgroups to fill the device several times) against the tuner's strip
+    // prefix, writing labels that the real launch overwrites.
     const int64_t trial_n = n < ((int64_t)1 << 19) ? n : ((int64_t)1 << 19);
     PairloopArgs a{};
     a.rec32 = set->rec32;
     a.rec64 = set->rec64;
-    a.surf = set->surf;
-    a.n_surf = set->n_surf;
+    a.surf = set->tune_surf + (fp64 ? 1 : 0);
+    a.n_surf = 1;
     a.x = x;
     a.y = y;
     a.z = z;
