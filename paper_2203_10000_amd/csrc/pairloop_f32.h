@@ -94,6 +94,7 @@ __device__ __forceinline__ TriRec load_rec(const CRec32 *p) {
 template <int P>
 __device__ __forceinline__ void f32_step(const Vtx (&O)[P], const Vtx (&N)[P], Vtx (&F)[P],
                                          float (&e01)[P], float (&rr01)[P], float (&acc)[P],
+                                         float (&accn)[P],
                                          const TriRec &rec, const float (&px)[P],
                                          const float (&py)[P], const float (&pz)[P],
                                          const uint64_t (&good_mask)[P], float kap,
@@ -135,7 +136,7 @@ __device__ __forceinline__ void f32_step(const Vtx (&O)[P], const Vtx (&N)[P], V
             const bool ill = fmaxf(fabsf(n1), fabsf(dd[j])) <= thr;
             const bool cut = fabsf(ang) > branch_cut;
             cmask[j] |= (ballot(ill) | ballot(cut)) & good_mask[j];
-            acc[j] += ang;
+            accn[j] += ang;
         }
     }
 #pragma unroll
@@ -165,7 +166,9 @@ __device__ __forceinline__ void surface_sum(const CRec32 *rec, int64_t rec_begin
         const float h0 = h->v[0], h1 = h->v[1], h2 = h->v[2];
         const float h3 = h->v[3], h4 = h->v[4], h5 = h->v[5];
         Vtx A[P], B[P], C[P];
-        float e01[P], rr01[P], acc[P];
+        // Small-angle terms and full-atan2 terms go to separate float sums,
+        // so the two paths do not merge one register (no copy per step).
+        float e01[P], rr01[P], acc[P], accn[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             A[j].x = h0 - px[j]; A[j].y = h1 - py[j]; A[j].z = h2 - pz[j];
@@ -175,6 +178,7 @@ __device__ __forceinline__ void surface_sum(const CRec32 *rec, int64_t rec_begin
             e01[j] = fmaf(A[j].x, B[j].x, fmaf(A[j].y, B[j].y, A[j].z * B[j].z));
             rr01[j] = A[j].r * B[j].r;
             acc[j] = 0.0f;
+            accn[j] = 0.0f;
         }
         // Triangle records are prefetched one step ahead: each step first
         // waits for the scalar loads in flight (the record it is about to
@@ -190,26 +194,26 @@ __device__ __forceinline__ void surface_sum(const CRec32 *rec, int64_t rec_begin
             __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
             c1 = load_rec(tr + (t + 1));
             __builtin_amdgcn_sched_barrier(0);     // keep the step's arithmetic below
-            f32_step<P>(A, B, C, e01, rr01, acc, c0, px, py, pz, good_mask, kap, branch_cut, cmask);
+            f32_step<P>(A, B, C, e01, rr01, acc, accn, c0, px, py, pz, good_mask, kap, branch_cut, cmask);
             __builtin_amdgcn_s_waitcnt(0xc07f);
             c2 = load_rec(tr + (t + 2));
             __builtin_amdgcn_sched_barrier(0);
-            f32_step<P>(B, C, A, e01, rr01, acc, c1, px, py, pz, good_mask, kap, branch_cut, cmask);
+            f32_step<P>(B, C, A, e01, rr01, acc, accn, c1, px, py, pz, good_mask, kap, branch_cut, cmask);
             __builtin_amdgcn_s_waitcnt(0xc07f);
             c0 = load_rec(tr + (t + 3 < last ? t + 3 : last));
             __builtin_amdgcn_sched_barrier(0);
-            f32_step<P>(C, A, B, e01, rr01, acc, c2, px, py, pz, good_mask, kap, branch_cut, cmask);
+            f32_step<P>(C, A, B, e01, rr01, acc, accn, c2, px, py, pz, good_mask, kap, branch_cut, cmask);
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);
         if (t < m) {
-            f32_step<P>(A, B, C, e01, rr01, acc, c0, px, py, pz, good_mask, kap, branch_cut, cmask);
+            f32_step<P>(A, B, C, e01, rr01, acc, accn, c0, px, py, pz, good_mask, kap, branch_cut, cmask);
             if (t + 1 < m) {
                 c1 = load_rec(tr + (t + 1));
-                f32_step<P>(B, C, A, e01, rr01, acc, c1, px, py, pz, good_mask, kap, branch_cut, cmask);
+                f32_step<P>(B, C, A, e01, rr01, acc, accn, c1, px, py, pz, good_mask, kap, branch_cut, cmask);
             }
         }
 #pragma unroll
-        for (int j = 0; j < P; ++j) S[j] += (double)acc[j];
+        for (int j = 0; j < P; ++j) S[j] += (double)acc[j] + (double)accn[j];
         r += m + 1;
     }
 }
