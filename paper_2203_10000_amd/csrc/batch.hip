@@ -145,12 +145,19 @@ __global__ __launch_bounds__(kRecheckThreads) void k_batch_recheck(BatchArgs a) 
             const int k = __builtin_ctzll(f);
             f &= f - 1;
             const SurfaceDev sd = in.surf[k];
-            const int64_t per = (sd.rec_end - sd.rec_begin + kRecheckThreads - 1) / kRecheckThreads;
-            const int64_t r_lo = sd.rec_begin + (int64_t)tid * per;
-            const int64_t r_hi = r_lo + per < sd.rec_end ? r_lo + per : sd.rec_end;
+            double part = 0.0;
             int on = 0;
-            const double part = f64_record_range(in.rec64, in.strip_off, sd.strip_begin,
-                                                 sd.strip_end, r_lo, r_hi, pd, praw, &on, &n_exact);
+            for (int64_t s = sd.strip_begin + tid; s < sd.strip_end; s += kRecheckThreads) {
+                const int64_t r = in.strip_off[s];
+                const double *h = in.rec64[r].v;
+                const int m = __double_as_longlong(h[6]) & 0x7fffffff;
+                StripF64 st;
+                f64_strip_head(st, h, pd);
+                double acc = 0.0;
+                for (int t = 1; t <= m; ++t)
+                    acc += f64_strip_tri(st, in.rec64[r + t].v, pd, praw, &on, &n_exact);
+                part += acc;
+            }
             red[tid] = part;
             on = __syncthreads_or(on);
             for (int w = kRecheckThreads / 2; w > 0; w >>= 1) {

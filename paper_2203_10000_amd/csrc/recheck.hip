@@ -3,9 +3,9 @@
 //
 // One workgroup per flagged point (grid-stride over the device-side count, so
 // no host round trip sizes the launch).  For each flagged surface the 256
-// threads take equal ranges of the surface's record stream (a range may begin
-// inside a strip), each sums its range in double, and an LDS tree reduces the
-// 256 partial sums in a fixed order: the result does not depend on timing.
+// threads take the surface's strips round-robin, each sums its strips in
+// double along the strip, and an LDS tree reduces the 256 partial sums in a
+// fixed order: the result does not depend on timing.
 #include <hip/hip_runtime.h>
 
 #include "sal_internal.h"
@@ -33,13 +33,19 @@ __global__ __launch_bounds__(kThreads) void k_recheck_f64(RecheckArgs a) {
             const int k = __builtin_ctzll(f);
             f &= f - 1;
             const SurfaceDev sd = a.surf[k];
-            // equal record ranges per thread, whatever the strip lengths
-            const int64_t per = (sd.rec_end - sd.rec_begin + kThreads - 1) / kThreads;
-            const int64_t r_lo = sd.rec_begin + (int64_t)tid * per;
-            const int64_t r_hi = r_lo + per < sd.rec_end ? r_lo + per : sd.rec_end;
+            double part = 0.0;
             int on = 0;
-            const double part = f64_record_range(a.rec64, a.strip_off, sd.strip_begin, sd.strip_end,
-                                                 r_lo, r_hi, p, praw, &on, &n_exact);
+            for (int64_t s = sd.strip_begin + tid; s < sd.strip_end; s += kThreads) {
+                const int64_t r = a.strip_off[s];
+                const double *h = a.rec64[r].v;
+                const int m = __double_as_longlong(h[6]) & 0x7fffffff;
+                StripF64 st;
+                f64_strip_head(st, h, p);
+                double acc = 0.0;
+                for (int t = 1; t <= m; ++t)
+                    acc += f64_strip_tri(st, a.rec64[r + t].v, p, praw, &on, &n_exact);
+                part += acc;
+            }
             red[tid] = part;
             on = __syncthreads_or(on);
             for (int w = kThreads / 2; w > 0; w >>= 1) {

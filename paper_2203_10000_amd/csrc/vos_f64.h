@@ -28,29 +28,23 @@ struct StripF64 {
     float X[3], Y[3];           // raw coordinates (exact predicate inputs)
 };
 
-// Strip window with older vertex X and newer vertex Y (three doubles each).
-__device__ __forceinline__ void f64_strip_window(StripF64 &s, const double *X, const double *Y,
-                                                 const double *p) {
-    s.dx0 = X[0] - p[0];
-    s.dy0 = X[1] - p[1];
-    s.dz0 = X[2] - p[2];
-    s.dx1 = Y[0] - p[0];
-    s.dy1 = Y[1] - p[1];
-    s.dz1 = Y[2] - p[2];
+__device__ __forceinline__ void f64_strip_head(StripF64 &s, const double *h, const double *p) {
+    s.dx0 = h[0] - p[0];
+    s.dy0 = h[1] - p[1];
+    s.dz0 = h[2] - p[2];
+    s.dx1 = h[3] - p[0];
+    s.dy1 = h[4] - p[1];
+    s.dz1 = h[5] - p[2];
     s.r0 = sqrt(s.dx0 * s.dx0 + s.dy0 * s.dy0 + s.dz0 * s.dz0);
     s.r1 = sqrt(s.dx1 * s.dx1 + s.dy1 * s.dy1 + s.dz1 * s.dz1);
     s.e01 = s.dx0 * s.dx1 + s.dy0 * s.dy1 + s.dz0 * s.dz1;
     s.rr01 = s.r0 * s.r1;
-    s.X[0] = (float)X[0];
-    s.X[1] = (float)X[1];
-    s.X[2] = (float)X[2];
-    s.Y[0] = (float)Y[0];
-    s.Y[1] = (float)Y[1];
-    s.Y[2] = (float)Y[2];
-}
-
-__device__ __forceinline__ void f64_strip_head(StripF64 &s, const double *h, const double *p) {
-    f64_strip_window(s, h, h + 3, p);
+    s.X[0] = (float)h[0];
+    s.X[1] = (float)h[1];
+    s.X[2] = (float)h[2];
+    s.Y[0] = (float)h[3];
+    s.Y[1] = (float)h[4];
+    s.Y[2] = (float)h[5];
 }
 
 // Out-of-line exact resolution of a triangle whose N sign is uncertain.
@@ -99,49 +93,6 @@ __device__ __forceinline__ double f64_strip_tri(StripF64 &s, const double *t, co
     s.X[0] = s.Y[0]; s.X[1] = s.Y[1]; s.X[2] = s.Y[2];
     s.Y[0] = (float)t[0]; s.Y[1] = (float)t[1]; s.Y[2] = (float)t[2];
     return half;
-}
-
-// Sum of atan2(N, D) over the records [r_lo, r_hi) of one surface (strip
-// heads and triangle records interleaved; strip_off[s_lo .. s_hi) are the
-// surface's strip heads).  The range may start inside a strip: the window is
-// rebuilt from the strip head or the two preceding triangle records, so a
-// surface can be cut into equal record ranges whatever its strip lengths.
-__device__ __forceinline__ double f64_record_range(const Rec64 *rec, const int64_t *strip_off,
-                                                   int64_t s_lo, int64_t s_hi, int64_t r_lo,
-                                                   int64_t r_hi, const double *p,
-                                                   const float *praw, int *on,
-                                                   unsigned *n_exact) {
-    if (r_lo >= r_hi) return 0.0;
-    int64_t lo = s_lo, hi = s_hi - 1;   // last strip whose head is <= r_lo
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (strip_off[mid] <= r_lo) lo = mid;
-        else hi = mid - 1;
-    }
-    int64_t head = strip_off[lo];
-    int64_t next_head = lo + 1 < s_hi ? strip_off[lo + 1] : r_hi;
-    StripF64 st;
-    int64_t r = r_lo;
-    if (r == head) {
-        f64_strip_head(st, rec[head].v, p);
-        ++r;
-    } else {
-        const int64_t j = r - head - 1;   // triangle index of record r in its strip
-        const double *X = j == 0 ? rec[head].v : (j == 1 ? rec[head].v + 3 : rec[r - 2].v);
-        const double *Y = j == 0 ? rec[head].v + 3 : rec[r - 1].v;
-        f64_strip_window(st, X, Y, p);
-    }
-    double acc = 0.0;
-    for (; r < r_hi; ++r) {
-        if (r == next_head) {
-            ++lo;
-            next_head = lo + 1 < s_hi ? strip_off[lo + 1] : r_hi;
-            f64_strip_head(st, rec[r].v, p);
-            continue;
-        }
-        acc += f64_strip_tri(st, rec[r].v, p, praw, on, n_exact);
-    }
-    return acc;
 }
 
 }  // namespace sal
