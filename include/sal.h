@@ -164,6 +164,8 @@ typedef struct sal_label_stats {
     int64_t n_band_flags;      /* pairs flagged by |w - T| < recheck_band */
     int64_t n_cond_flags;      /* pairs flagged by an ill-conditioned triangle */
     int64_t n_exact_fallbacks; /* triangle evaluations that needed the exact sign */
+    int64_t n_recheck_f64_terms; /* triangle terms of rechecked pairs evaluated in
+                                    double (the others are certified float32) */
     float ms_pairloop;         /* device time of the pair loop */
     float ms_recheck;          /* device time of the FP64 recheck */
     float ms_total;            /* device time from the pair loop's start to the

@@ -54,7 +54,8 @@ class LabelStats(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("n_recheck_points", ctypes.c_int64), ("n_recheck_pairs", ctypes.c_int64),
                 ("n_band_flags", ctypes.c_int64), ("n_cond_flags", ctypes.c_int64),
-                ("n_exact_fallbacks", ctypes.c_int64), ("ms_pairloop", ctypes.c_float),
+                ("n_exact_fallbacks", ctypes.c_int64),
+                ("n_recheck_f64_terms", ctypes.c_int64), ("ms_pairloop", ctypes.c_float),
                 ("ms_recheck", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("points_per_lane", ctypes.c_int32), ("block_waves", ctypes.c_int32)]
 

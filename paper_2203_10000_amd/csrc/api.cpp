@@ -87,6 +87,7 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     SAL_HIP(launch_pairloop_f32(a, opt.points_per_lane, opt.block_waves, stream));
     if (ev_mid) SAL_HIP(hipEventRecord(ev_mid, stream));
     RecheckArgs r{};
+    r.rec32 = set->rec32;
     r.rec64 = set->rec64;
     r.surf = set->surf;
     r.strip_off = set->strip_off;
@@ -95,6 +96,7 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     r.z = z;
     r.n = n;
     r.threshold = opt.threshold;
+    r.kappa = (float)opt.kappa;
     r.labels = labels;
     r.winding = a.winding;
     r.winding_type = a.winding_type;
@@ -292,6 +294,7 @@ sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_
         stats->n_band_flags = (int64_t)c[kCntBand];
         stats->n_cond_flags = (int64_t)c[kCntCond];
         stats->n_exact_fallbacks = (int64_t)c[kCntExact];
+        stats->n_recheck_f64_terms = (int64_t)c[kCntRecheckF64];
         SAL_HIP(hipEventElapsedTime(&stats->ms_pairloop, ctx->ev[0], ctx->ev[1]));
         SAL_HIP(hipEventElapsedTime(&stats->ms_total, ctx->ev[0], ctx->ev[2]));
         stats->ms_recheck = stats->ms_total - stats->ms_pairloop;

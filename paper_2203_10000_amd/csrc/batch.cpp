@@ -290,6 +290,7 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
                 stats[i].n_band_flags = (int64_t)ci[kCntBand];
                 stats[i].n_cond_flags = (int64_t)ci[kCntCond];
                 stats[i].n_exact_fallbacks = (int64_t)ci[kCntExact];
+                stats[i].n_recheck_f64_terms = (int64_t)ci[kCntRecheckF64];
                 stats[i].ms_total = ms;   // the whole batch (one launch sequence)
                 stats[i].ms_pairloop = ms;
                 stats[i].points_per_lane = 1;   // one point per lane, 4 wavefronts per workgroup

@@ -12,6 +12,7 @@
 
 #include "batch_internal.h"
 #include "pairloop_f32.h"
+#include "recheck_mixed.h"
 #include "vos_f64.h"
 
 namespace sal {
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(kRecheckThreads) void k_batch_recheck(BatchArgs a) 
     const int tid = threadIdx.x;
     int64_t count = (int64_t)a.counters[kCntFlagged];
     if (count > a.total_points) count = a.total_points;
+    const float branch_cut = mixed::kPiF - 0.25f * a.kappa;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         const FlagEntry e = a.flag_list[i];
         const int ii = find_inst(a.insts, a.n_inst, e.idx);
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kRecheckThreads) void k_batch_recheck(BatchArgs a) 
         const double pd[3] = {praw[0], praw[1], praw[2]};
         uint64_t enc = e.enc;
         uint64_t f = e.flg;
-        unsigned n_exact = 0;
+        unsigned n_exact = 0, n_f64 = 0;
         while (f) {
             const int k = __builtin_ctzll(f);
             f &= f - 1;
@@ -149,14 +151,9 @@ __global__ __launch_bounds__(kRecheckThreads) void k_batch_recheck(BatchArgs a) 
             int on = 0;
             for (int64_t s = sd.strip_begin + tid; s < sd.strip_end; s += kRecheckThreads) {
                 const int64_t r = in.strip_off[s];
-                const double *h = in.rec64[r].v;
-                const int m = __double_as_longlong(h[6]) & 0x7fffffff;
-                StripF64 st;
-                f64_strip_head(st, h, pd);
-                double acc = 0.0;
-                for (int t = 1; t <= m; ++t)
-                    acc += f64_strip_tri(st, in.rec64[r + t].v, pd, praw, &on, &n_exact);
-                part += acc;
+                const int m = __float_as_int(in.rec32[r].v[6]);
+                part += mixed::strip_sum(in.rec32, in.rec64, r, m, praw, pd, a.kappa, branch_cut,
+                                         &on, &n_exact, &n_f64);
             }
             red[tid] = part;
             on = __syncthreads_or(on);
@@ -171,6 +168,7 @@ __global__ __launch_bounds__(kRecheckThreads) void k_batch_recheck(BatchArgs a) 
         }
         unsigned long long *c = a.inst_counters + (int64_t)ii * kNumCounters;
         if (n_exact) atomicAdd(&c[kCntExact], (unsigned long long)n_exact);
+        if (n_f64) atomicAdd(&c[kCntRecheckF64], (unsigned long long)n_f64);
         if (tid == 0) {
             in.labels[p] = enc ? in.surf_label[63 - __builtin_clzll(enc)] : 0;
             atomicAdd(&c[kCntRecheck], (unsigned long long)__popcll(e.flg));

@@ -1,5 +1,7 @@
-// FP64 recheck of the (point, surface) pairs the float32 pass could not
-// certify, and the final label of those points.
+// Recheck of the (point, surface) pairs the float32 pass could not certify,
+// and the final label of those points: every triangle term is recomputed,
+// in float32 where float32 certifies it and in double (with the exact-sign
+// guard) where it does not (recheck_mixed.h).
 //
 // One workgroup per flagged point (grid-stride over the device-side count, so
 // no host round trip sizes the launch).  For each flagged surface the 256
@@ -8,8 +10,8 @@
 // fixed order: the result does not depend on timing.
 #include <hip/hip_runtime.h>
 
+#include "recheck_mixed.h"
 #include "sal_internal.h"
-#include "vos_f64.h"
 
 namespace sal {
 namespace {
@@ -22,7 +24,8 @@ __global__ __launch_bounds__(kThreads) void k_recheck_f64(RecheckArgs a) {
     const int tid = threadIdx.x;
     int64_t count = (int64_t)a.counters[kCntFlagged];
     if (count > a.n) count = a.n;
-    unsigned n_exact = 0;
+    unsigned n_exact = 0, n_f64 = 0;
+    const float branch_cut = mixed::kPiF - 0.25f * a.kappa;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         const FlagEntry e = a.flag_list[i];
         const float praw[3] = {a.x[e.idx], a.y[e.idx], a.z[e.idx]};
@@ -37,14 +40,9 @@ __global__ __launch_bounds__(kThreads) void k_recheck_f64(RecheckArgs a) {
             int on = 0;
             for (int64_t s = sd.strip_begin + tid; s < sd.strip_end; s += kThreads) {
                 const int64_t r = a.strip_off[s];
-                const double *h = a.rec64[r].v;
-                const int m = __double_as_longlong(h[6]) & 0x7fffffff;
-                StripF64 st;
-                f64_strip_head(st, h, p);
-                double acc = 0.0;
-                for (int t = 1; t <= m; ++t)
-                    acc += f64_strip_tri(st, a.rec64[r + t].v, p, praw, &on, &n_exact);
-                part += acc;
+                const int m = __float_as_int(a.rec32[r].v[6]);
+                part += mixed::strip_sum(a.rec32, a.rec64, r, m, praw, p, a.kappa, branch_cut,
+                                         &on, &n_exact, &n_f64);
             }
             red[tid] = part;
             on = __syncthreads_or(on);
@@ -71,6 +69,7 @@ __global__ __launch_bounds__(kThreads) void k_recheck_f64(RecheckArgs a) {
         }
     }
     if (n_exact) atomicAdd(&a.counters[kCntExact], (unsigned long long)n_exact);
+    if (n_f64) atomicAdd(&a.counters[kCntRecheckF64], (unsigned long long)n_f64);
 }
 
 }  // namespace

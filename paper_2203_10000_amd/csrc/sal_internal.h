@@ -72,6 +72,7 @@ enum Counter {
     kCntCond = 2,      // pairs flagged by ill-conditioned triangles
     kCntExact = 3,     // exact-sign evaluations
     kCntRecheck = 4,   // pairs recomputed in FP64
+    kCntRecheckF64 = 5,  // triangle terms of rechecked pairs evaluated in double
     kNumCounters = 8
 };
 
@@ -97,6 +98,7 @@ struct PairloopArgs {
 };
 
 struct RecheckArgs {
+    const Rec32 *__restrict__ rec32;
     const Rec64 *__restrict__ rec64;
     const SurfaceDev *__restrict__ surf;
     const int64_t *__restrict__ strip_off;  // record index of every strip head
@@ -105,6 +107,7 @@ struct RecheckArgs {
     const float *__restrict__ z;
     int64_t n;
     double threshold;
+    float kappa;
     int32_t *__restrict__ labels;
     void *__restrict__ winding;
     int winding_type;

@@ -28,23 +28,29 @@ struct StripF64 {
     float X[3], Y[3];           // raw coordinates (exact predicate inputs)
 };
 
-__device__ __forceinline__ void f64_strip_head(StripF64 &s, const double *h, const double *p) {
-    s.dx0 = h[0] - p[0];
-    s.dy0 = h[1] - p[1];
-    s.dz0 = h[2] - p[2];
-    s.dx1 = h[3] - p[0];
-    s.dy1 = h[4] - p[1];
-    s.dz1 = h[5] - p[2];
+// Strip window with older vertex X and newer vertex Y (three doubles each).
+__device__ __forceinline__ void f64_strip_window(StripF64 &s, const double *X, const double *Y,
+                                                 const double *p) {
+    s.dx0 = X[0] - p[0];
+    s.dy0 = X[1] - p[1];
+    s.dz0 = X[2] - p[2];
+    s.dx1 = Y[0] - p[0];
+    s.dy1 = Y[1] - p[1];
+    s.dz1 = Y[2] - p[2];
     s.r0 = sqrt(s.dx0 * s.dx0 + s.dy0 * s.dy0 + s.dz0 * s.dz0);
     s.r1 = sqrt(s.dx1 * s.dx1 + s.dy1 * s.dy1 + s.dz1 * s.dz1);
     s.e01 = s.dx0 * s.dx1 + s.dy0 * s.dy1 + s.dz0 * s.dz1;
     s.rr01 = s.r0 * s.r1;
-    s.X[0] = (float)h[0];
-    s.X[1] = (float)h[1];
-    s.X[2] = (float)h[2];
-    s.Y[0] = (float)h[3];
-    s.Y[1] = (float)h[4];
-    s.Y[2] = (float)h[5];
+    s.X[0] = (float)X[0];
+    s.X[1] = (float)X[1];
+    s.X[2] = (float)X[2];
+    s.Y[0] = (float)Y[0];
+    s.Y[1] = (float)Y[1];
+    s.Y[2] = (float)Y[2];
+}
+
+__device__ __forceinline__ void f64_strip_head(StripF64 &s, const double *h, const double *p) {
+    f64_strip_window(s, h, h + 3, p);
 }
 
 // Out-of-line exact resolution of a triangle whose N sign is uncertain.
