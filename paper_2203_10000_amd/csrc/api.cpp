@@ -20,16 +20,32 @@ sal_status hip_error(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? SAL_ERR_OUT_OF_MEMORY : SAL_ERR_DEVICE;
 }
 
+// The flag list and the pair-major recheck scratch: a quarter of the flag
+// capacity in pairs (a point more often has one flagged surface than two; a
+// recheck with more pairs than that takes the per-point form).
 sal_status ensure_flag_capacity(sal_context *ctx, int64_t n) {
-    if (n <= ctx->flag_cap) return SAL_OK;
+    if (n <= ctx->flag_cap && ctx->rc_seg) return SAL_OK;
     SAL_HIP(hipStreamSynchronize(ctx->stream));
-    if (ctx->flag_list) SAL_HIP(hipFree(ctx->flag_list));
-    ctx->flag_list = nullptr;
+    auto release = [](void *&p) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    };
+    release((void *&)ctx->flag_list);
+    release((void *&)ctx->rc_pairs);
+    release((void *&)ctx->rc_out);
+    release((void *&)ctx->rc_res);
     ctx->batch_graph_key = 0;   // a captured batch graph points at the old list
     ctx->flag_cap = 0;
+    ctx->rc_pair_cap = 0;
     const int64_t cap = n < 4096 ? 4096 : n;
+    const int64_t pcap = cap / 4 + 64 * kMaxSurfaces;
     SAL_HIP(hipMalloc((void **)&ctx->flag_list, (size_t)cap * sizeof(FlagEntry)));
+    SAL_HIP(hipMalloc((void **)&ctx->rc_res, (size_t)cap * sizeof(unsigned long long)));
+    SAL_HIP(hipMalloc((void **)&ctx->rc_pairs, (size_t)pcap * sizeof(RecheckPair)));
+    SAL_HIP(hipMalloc((void **)&ctx->rc_out, (size_t)pcap * sizeof(RecheckOut)));
+    if (!ctx->rc_seg) SAL_HIP(hipMalloc((void **)&ctx->rc_seg, sizeof(RecheckSeg)));
     ctx->flag_cap = cap;
+    ctx->rc_pair_cap = pcap;
     return SAL_OK;
 }
 
@@ -102,6 +118,12 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     r.winding_type = a.winding_type;
     r.flag_list = ctx->flag_list;
     r.counters = ctx->counters;
+    r.n_surf = set->n_surf;
+    r.pairs = ctx->rc_pairs;
+    r.pair_out = ctx->rc_out;
+    r.res = ctx->rc_res;
+    r.seg = ctx->rc_seg;
+    r.pair_cap = ctx->rc_pair_cap;
     const int64_t grid = n < (int64_t)ctx->n_cu * 8 ? n : (int64_t)ctx->n_cu * 8;
     SAL_HIP(launch_recheck_f64(r, (int)grid, stream));
     return SAL_OK;
@@ -219,6 +241,10 @@ void sal_context_destroy(sal_context *ctx) {
     for (auto &ev : ctx->ev)
         if (ev) (void)hipEventDestroy(ev);
     if (ctx->flag_list) (void)hipFree(ctx->flag_list);
+    if (ctx->rc_pairs) (void)hipFree(ctx->rc_pairs);
+    if (ctx->rc_out) (void)hipFree(ctx->rc_out);
+    if (ctx->rc_res) (void)hipFree(ctx->rc_res);
+    if (ctx->rc_seg) (void)hipFree(ctx->rc_seg);
     if (ctx->counters) (void)hipFree(ctx->counters);
     if (ctx->tune_counters) (void)hipFree(ctx->tune_counters);
     if (ctx->batch_graph) (void)hipGraphExecDestroy(ctx->batch_graph);

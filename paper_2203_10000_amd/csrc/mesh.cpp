@@ -361,6 +361,12 @@ sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set
     uint64_t key = mix(0x5a1d5a1dull, set->uid);
     key = mixp(key, ctx);
     key = mixp(key, ctx->flag_list);
+    key = mixp(key, ctx->rc_pairs);
+    key = mixp(key, ctx->rc_out);
+    key = mixp(key, ctx->rc_res);
+    key = mixp(key, ctx->rc_seg);
+    key = mix(key, (uint64_t)ctx->flag_cap);
+    key = mix(key, (uint64_t)ctx->rc_pair_cap);
     key = mixp(key, ctx->counters);
     key = mix(key, (uint64_t)opt.precision);
     key = mixd(key, opt.threshold);

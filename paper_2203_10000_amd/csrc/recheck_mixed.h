@@ -22,16 +22,26 @@ constexpr float kA0 = 0.0625f;
 constexpr float kA1 = -8.1380208333e-05f;
 constexpr float kA2 = 1.9073486328e-07f;
 
+struct F64Term {
+    double half;      // atan2(N, D)
+    int on;           // the point lies on the closed triangle
+    unsigned exact;   // exact-sign evaluations made
+};
+
 // One triangle (X, Y, Z) in double with the exact-sign guard; Z and the
-// double normal come from its FP64 record.  Out of line: it is rare, and
-// inlined its registers would count against the float32 walk.
-__device__ __noinline__ double f64_triangle(const float *X, const float *Y, const double *rec,
-                                            const double *pd, const float *pf, int *on,
-                                            unsigned *n_exact) {
-    const double Xd[3] = {X[0], X[1], X[2]}, Yd[3] = {Y[0], Y[1], Y[2]};
+// double normal come from its FP64 record.  Out of line and by value: it is
+// rare, and inlined its registers would count against the float32 walk.
+__device__ __noinline__ F64Term f64_triangle(float x0, float x1, float x2, float y0, float y1,
+                                             float y2, const double *rec, float px, float py,
+                                             float pz) {
+    const double Xd[3] = {x0, x1, x2}, Yd[3] = {y0, y1, y2};
+    const double pd[3] = {px, py, pz};
+    const float pf[3] = {px, py, pz};
     StripF64 st;
     f64_strip_window(st, Xd, Yd, pd);
-    return f64_strip_tri(st, rec, pd, pf, on, n_exact);
+    F64Term r{0.0, 0, 0u};
+    r.half = f64_strip_tri(st, rec, pd, pf, &r.on, &r.exact);
+    return r;
 }
 
 // Sum of atan2(N, D) over the m triangles of the strip whose head is record r,
@@ -74,7 +84,11 @@ __device__ __forceinline__ double strip_sum(const Rec32 *__restrict__ rec32,
             const bool ill = fmaxf(fabsf(n1), fabsf(dd)) <= thr;
             const bool cut = fabsf(ang) > branch_cut;
             if (ill || cut) {
-                accd += f64_triangle(X, Y, rec64[r + t].v, pd, pf, on, n_exact);
+                const F64Term d = f64_triangle(X[0], X[1], X[2], Y[0], Y[1], Y[2], rec64[r + t].v,
+                                               pf[0], pf[1], pf[2]);
+                accd += d.half;
+                *on |= d.on;
+                *n_exact += d.exact;
                 *n_f64 += 1;
             } else {
                 accf += ang;

@@ -12,6 +12,12 @@ struct sal_context {
     hipEvent_t ev[8] = {};
     sal::FlagEntry *flag_list = nullptr;
     int64_t flag_cap = 0;
+    // pair-major recheck scratch (grows with the flag list)
+    sal::RecheckPair *rc_pairs = nullptr;
+    sal::RecheckOut *rc_out = nullptr;
+    unsigned long long *rc_res = nullptr;
+    sal::RecheckSeg *rc_seg = nullptr;
+    int64_t rc_pair_cap = 0;
     unsigned long long *counters = nullptr;  // sal::kNumCounters
     unsigned long long *tune_counters = nullptr;
     int n_cu = 0;

@@ -97,6 +97,26 @@ struct PairloopArgs {
     unsigned long long *__restrict__ counters;
 };
 
+// Pair-major recheck: the flagged (point, surface) pairs grouped by surface,
+// each group padded to a multiple of 64 so that the 64 pairs of a wavefront
+// share one surface and its records can be scalar loads.
+struct RecheckPair {
+    int32_t entry;   // flag-list index; -1 = padding
+    int32_t surf;
+};
+struct RecheckOut {
+    double sum;      // sum of atan2(N, D) over the surface (half the solid angle)
+    int32_t on;      // the point lies on the surface
+    uint32_t pad;
+};
+struct RecheckSeg {
+    unsigned long long count[kMaxSurfaces];
+    unsigned long long cursor[kMaxSurfaces];
+    unsigned long long off[kMaxSurfaces];
+    unsigned long long total;     // padded pair count
+    unsigned long long overflow;  // more pairs than capacity: the per-point form runs instead
+};
+
 struct RecheckArgs {
     const Rec32 *__restrict__ rec32;
     const Rec64 *__restrict__ rec64;
@@ -113,12 +133,20 @@ struct RecheckArgs {
     int winding_type;
     const FlagEntry *__restrict__ flag_list;
     unsigned long long *__restrict__ counters;
+    int n_surf;
+    RecheckPair *__restrict__ pairs;      // [pair_cap]
+    RecheckOut *__restrict__ pair_out;    // [pair_cap]
+    unsigned long long *__restrict__ res; // [flag capacity]: enclosed bits per flagged point
+    RecheckSeg *__restrict__ seg;
+    int64_t pair_cap;
 };
 
 // Kernel launchers (pairloop.hip, recheck.hip).
 hipError_t launch_pairloop_f32(const PairloopArgs &a, int points_per_lane, int block_waves,
                                hipStream_t s);
 hipError_t launch_pairloop_f64(const PairloopArgs &a, int block_waves, hipStream_t s);
+// The whole recheck: pair-major when the pairs fit, else one workgroup per
+// flagged point; grid_blocks sizes the grid-stride kernels.
 hipError_t launch_recheck_f64(const RecheckArgs &a, int grid_blocks, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 
