@@ -124,6 +124,7 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     r.res = ctx->rc_res;
     r.seg = ctx->rc_seg;
     r.pair_cap = ctx->rc_pair_cap;
+    r.target_waves = (int64_t)ctx->n_cu * 32;
     const int64_t grid = n < (int64_t)ctx->n_cu * 8 ? n : (int64_t)ctx->n_cu * 8;
     SAL_HIP(launch_recheck_f64(r, (int)grid, stream));
     return SAL_OK;

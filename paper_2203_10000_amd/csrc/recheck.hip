@@ -82,7 +82,20 @@ __global__ void k_rc_scan(RecheckArgs a) {
     }
     a.seg->off[k] = off;
     if (k == 0) {
+        // Few pairs: cut each surface into strip ranges so that chunks x
+        // splits wavefronts fill the GPU; the partial sums need splits slots
+        // per pair, so splits <= capacity / pairs.
+        const unsigned long long chunks = total / 64ull;
+        unsigned long long sp = 1;
+        if (chunks > 0) {
+            sp = ((unsigned long long)a.target_waves + chunks - 1) / chunks;
+            if (sp > 16) sp = 16;
+            const unsigned long long room = (unsigned long long)a.pair_cap / total;
+            if (sp > room) sp = room;
+            if (sp < 1) sp = 1;
+        }
         a.seg->total = total;
+        a.seg->splits = sp;
         a.seg->overflow = total > (unsigned long long)a.pair_cap ? 1ull : 0ull;
     }
     if (total > (unsigned long long)a.pair_cap) return;
@@ -116,7 +129,8 @@ constexpr int kPairWaves = 4;   // wavefronts per workgroup of k_rc_pairs
 
 __global__ __launch_bounds__(64 * kPairWaves) void k_rc_pairs(RecheckArgs a) {
     if (a.seg->overflow) return;
-    const int64_t chunks = (int64_t)(a.seg->total / 64ull);
+    const int64_t splits = (int64_t)a.seg->splits;
+    const int64_t items = (int64_t)(a.seg->total / 64ull) * splits;
     const int lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * kPairWaves +
                          __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
@@ -126,7 +140,9 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_rc_pairs(RecheckArgs a) {
     const float kap = a.kappa;
     const float branch_cut = mixed::kPiF - 0.25f * kap;
     unsigned n_exact = 0, n_f64 = 0;
-    for (int64_t c = wave; c < chunks; c += n_waves) {
+    for (int64_t it = wave; it < items; it += n_waves) {
+        const int64_t c = it / splits;     // 64-pair chunk
+        const int64_t j = it - c * splits; // strip range of the surface
         const RecheckPair pr = a.pairs[c * 64 + lane];
         const int k = __builtin_amdgcn_readfirstlane(pr.surf);
         const bool valid = pr.entry >= 0;
@@ -139,8 +155,10 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_rc_pairs(RecheckArgs a) {
         }
         double S = 0.0;
         int on = 0;
-        const int64_t rec_end = surf[k].rec_end;
-        for (int64_t r = surf[k].rec_begin; r < rec_end;) {
+        const int64_t sb = surf[k].strip_begin, n_strips = surf[k].strip_end - sb;
+        const int64_t s_lo = sb + n_strips * j / splits, s_hi = sb + n_strips * (j + 1) / splits;
+        const int64_t rec_end = s_hi < surf[k].strip_end ? a.strip_off[s_hi] : surf[k].rec_end;
+        for (int64_t r = s_lo < s_hi ? a.strip_off[s_lo] : rec_end; r < rec_end;) {
             const CRec32 *h = rec + r;
             const int m = __float_as_int(h->v[6]);
             float x0 = h->v[0], x1 = h->v[1], x2 = h->v[2];   // raw older vertex
@@ -203,7 +221,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_rc_pairs(RecheckArgs a) {
             o.sum = S;
             o.on = on;
             o.pad = 0u;
-            a.pair_out[c * 64 + lane] = o;
+            a.pair_out[(c * 64 + lane) * splits + j] = o;
         }
     }
     if (n_exact) atomicAdd(&a.counters[kCntExact], (unsigned long long)n_exact);
@@ -219,9 +237,16 @@ __global__ void k_rc_pair_final(RecheckArgs a) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
         const RecheckPair pr = a.pairs[q];
         if (pr.entry < 0) continue;
-        const RecheckOut o = a.pair_out[q];
-        const double w = o.sum * kInv2Pi;
-        if (o.on || w >= a.threshold) atomicOr(&a.res[pr.entry], 1ull << pr.surf);
+        const int64_t splits = (int64_t)a.seg->splits;
+        double sum = 0.0;
+        int on = 0;
+        for (int64_t j = 0; j < splits; ++j) {   // the strip ranges in order
+            const RecheckOut o = a.pair_out[q * splits + j];
+            sum += o.sum;
+            on |= o.on;
+        }
+        const double w = sum * kInv2Pi;
+        if (on || w >= a.threshold) atomicOr(&a.res[pr.entry], 1ull << pr.surf);
         if (a.winding) {
             const int64_t idx = a.flag_list[pr.entry].idx;
             const int64_t off = (int64_t)pr.surf * a.n + idx;

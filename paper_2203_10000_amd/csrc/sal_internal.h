@@ -115,6 +115,7 @@ struct RecheckSeg {
     unsigned long long off[kMaxSurfaces];
     unsigned long long total;     // padded pair count
     unsigned long long overflow;  // more pairs than capacity: the per-point form runs instead
+    unsigned long long splits;    // strip ranges per surface (more wavefronts for few pairs)
 };
 
 struct RecheckArgs {
@@ -139,6 +140,7 @@ struct RecheckArgs {
     unsigned long long *__restrict__ res; // [flag capacity]: enclosed bits per flagged point
     RecheckSeg *__restrict__ seg;
     int64_t pair_cap;
+    int64_t target_waves;                  // wavefronts the pair-major form aims for
 };
 
 // Kernel launchers (pairloop.hip, recheck.hip).
