@@ -231,31 +231,46 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int64_t *__restrict__ coun
     if (t == 1023) *total = part[1023];
 }
 
+// Ordered scatter of one tile: each wavefront takes a contiguous quarter of
+// the tile in 64-entry steps (coalesced reads), ranks its matches with
+// ballots, and the tile's indices are staged in LDS in index order, then
+// written out contiguously (coalesced writes).
+constexpr int kScanWaves = kScanThreads / 64;
+constexpr int kWaveItems = kScanTile / kScanWaves;
+
 __global__ __launch_bounds__(kScanThreads) void k_scatter(CompactSrc s, int64_t n,
                                                           const int64_t *__restrict__ n_dev,
                                                           const int64_t *__restrict__ offsets,
                                                           int32_t *__restrict__ out) {
-    __shared__ int part[kScanThreads];
+    __shared__ int32_t buf[kScanTile];
+    __shared__ int wave_total[kScanWaves];
     if (n_dev) n = *n_dev;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wv = (int)(threadIdx.x >> 6);
+    const int64_t wbase = (int64_t)blockIdx.x * kScanTile + (int64_t)wv * kWaveItems;
+    const uint64_t below = (1ull << lane) - 1ull;
     int cnt = 0;
-    for (int r = 0; r < kScanItems; ++r) {
-        const int64_t i = base + r;
-        if (i < n && pred(s, i)) ++cnt;
+    for (int r = 0; r < kWaveItems / 64; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        cnt += __popcll(__builtin_amdgcn_ballot_w64(i < n && pred(s, i)));
     }
-    part[threadIdx.x] = cnt;
+    if (lane == 0) wave_total[wv] = cnt;
     __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    int run = 0, total = 0;
+    for (int w = 0; w < kScanWaves; ++w) {
+        if (w < wv) run += wave_total[w];
+        total += wave_total[w];
     }
-    int64_t pos = offsets[blockIdx.x] + part[threadIdx.x] - cnt;
-    for (int r = 0; r < kScanItems; ++r) {
-        const int64_t i = base + r;
-        if (i < n && pred(s, i)) out[pos++] = (int32_t)i;
+    for (int r = 0; r < kWaveItems / 64; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        const bool p = i < n && pred(s, i);
+        const uint64_t m = __builtin_amdgcn_ballot_w64(p);
+        if (p) buf[run + __popcll(m & below)] = (int32_t)i;
+        run += __popcll(m);
     }
+    __syncthreads();
+    const int64_t o = offsets[blockIdx.x];
+    for (int j = (int)threadIdx.x; j < total; j += kScanThreads) out[o + j] = buf[j];
 }
 
 // Section 2.1.2: each listed leaf of level l becomes 8 level-(l+1) tetrahedra
