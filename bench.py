@@ -135,8 +135,19 @@ def _oracle_check(pts_np, surfaces, gpu_labels_np, n, rng, near_mask=None):
     if near_mask is not None and near_mask.any():
         near = np.nonzero(near_mask)[0]
         idx = np.unique(np.concatenate([idx, rng.choice(near, min(n, len(near)), replace=False)]))
-    want = oracle.label(np.ascontiguousarray(pts_np[:, idx]), surfaces)
+    threads = oracle.host_threads()
+    t0 = time.perf_counter()
+    want = oracle.label(np.ascontiguousarray(pts_np[:, idx]), surfaces, n_threads=threads)
+    dt = time.perf_counter() - t0
+    n_tri = sum(len(s.f) for s in surfaces)
+    _ORACLE_RATE.update({"value": len(idx) * n_tri / max(dt, 1e-9) / 1e9, "unit": "G pairs/s",
+                         "cores": threads, "kind": "oracle",
+                         "sample": "%d points x %d triangles, %.1f s" % (len(idx), n_tri, dt)})
     return int((gpu_labels_np[idx] != want).sum()), int(len(idx))
+
+
+# The oracle's rate on the last label check (reported beside the c3-c5 results).
+_ORACLE_RATE = {}
 
 
 def run_c3(args):
@@ -172,7 +183,8 @@ def run_c3(args):
             "max_level": lv, "pairs": pairs, "wall_s": wall,
             "g_pairs_per_s": pairs / wall / 1e9,
             "leaf_count_identity": n_leaves == lat.n_points + 7 * sum(x["n_boundary"] for x in st),
-            "oracle_sample_mismatches": mism, "oracle_sample": checked}
+            "oracle_sample_mismatches": mism, "oracle_sample": checked,
+            "oracle_rate": dict(_ORACLE_RATE)}
 
 
 def run_c4(args):
@@ -225,7 +237,8 @@ def run_c4(args):
                 "batched": {"s": t_batch, "g_pairs_per_s": pairs / t_batch / 1e9},
                 "batched_graph": {"s": t_graph, "g_pairs_per_s": pairs / t_graph / 1e9},
                 "batched_equals_per_instance": bool(same),
-                "oracle_sample_mismatches": mism, "oracle_sample": checked})
+                "oracle_sample_mismatches": mism, "oracle_sample": checked,
+                "oracle_rate": dict(_ORACLE_RATE)})
     return out
 
 
@@ -259,7 +272,8 @@ def run_c5(args):
                            "band_flags": st["n_band_flags"], "cond_flags": st["n_cond_flags"],
                            "exact_fallbacks": st["n_exact_fallbacks"],
                            "ms_pairloop": st["ms_pairloop"], "ms_recheck": st["ms_recheck"],
-                           "oracle_sample_mismatches": mism, "oracle_sample": checked}
+                           "oracle_sample_mismatches": mism, "oracle_sample": checked,
+                           "oracle_rate": dict(_ORACLE_RATE)}
     del near, lab
     progress("c5: lattice slab")
     nz = max(1, int(round(lat.cells[2] * args.c5_lattice_fraction)))
@@ -281,7 +295,8 @@ def run_c5(args):
     out["lattice_slab"] = {"cells": slab, "points": rs[0]["n_labeled"], "pairs": rs[0]["n_pairs"],
                            "wall_s": wall, "g_pairs_per_s": rs[0]["n_pairs"] / wall / 1e9,
                            "recheck_pairs": rs[0]["n_recheck_pairs"],
-                           "oracle_sample_mismatches": mism, "oracle_sample": checked}
+                           "oracle_sample_mismatches": mism, "oracle_sample": checked,
+                           "oracle_rate": dict(_ORACLE_RATE)}
     return out
 
 
