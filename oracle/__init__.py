@@ -60,6 +60,10 @@ def lib():
         L.oracle_radial_inside.argtypes = [ctypes.c_int64, f32p, f32p, f32p, f32p, f32p,
                                            ctypes.c_int64, i32p, ctypes.c_int, u8p]
         L.oracle_radial_inside.restype = None
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        L.oracle_enclosure.argtypes = [ctypes.c_int64, f32p, f32p, f32p, ctypes.c_int, i64p,
+                                       i64p, f32p, i32p, ctypes.c_double, ctypes.c_int, u64p]
+        L.oracle_enclosure.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -132,6 +136,30 @@ def label(points, surfaces, threshold=0.5, n_threads=0, want_w=False):
                        float(threshold), int(n_threads), out,
                        w.ctypes.data if want_w else None)
     return (out, w) if want_w else out
+
+
+def enclosure(points, surfaces, threshold=0.5, n_threads=0):
+    """uint64 [N]: bit s set when the point is enclosed by surface s (the
+    test of label(): w >= threshold or on the surface)."""
+    x, y, z = _soa(points)
+    n = x.size
+    vert_off, tri_off, verts, tris, _ = pack_surfaces(surfaces)
+    out = np.empty(n, dtype=np.uint64)
+    r = lib().oracle_enclosure(n, x, y, z, len(surfaces), vert_off, tri_off, verts, tris,
+                               float(threshold), int(n_threads), out)
+    if r < 0:
+        raise ValueError("at most 64 surfaces")
+    return out
+
+
+def mask_label(masks, surfaces):
+    """Label of each enclosure mask: the latest surface in the list whose bit
+    is set (surfaces outermost first), 0 when none is."""
+    masks = np.asarray(masks, dtype=np.uint64)
+    labs = np.zeros(masks.shape, dtype=np.int32)
+    for s, surf in enumerate(surfaces):
+        labs[(masks >> np.uint64(s)) & np.uint64(1) == 1] = surf.label
+    return labs
 
 
 def radial_inside(points, surface, n_threads=0):

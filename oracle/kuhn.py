@@ -242,3 +242,109 @@ def refine_relabel(lattice, label_fn, rounds):
         stats.append(dict(boundary=int(bmask.sum()), children=int(len(kids)),
                           leaves=int(len(leaves.keys)), labeled=int(len(kids))))
     return leaves, stats
+
+
+# ------------------------------------------------- node-based labeling
+# Section 2.1.3 as printed labels mesh nodes and calls a tetrahedron
+# contained in a surface when its four nodes are; nodes are identified by
+# integer coordinates on the finest grid any level can reach.
+MAX_LEVEL = 3
+_FINE = 1 << MAX_LEVEL
+
+
+def lattice_nodes_units(cells):
+    """All level-0 nodes [(nx+1)(ny+1)(nz+1), 3] in lattice units, x fastest."""
+    nx, ny, nz = cells
+    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
+                             indexing="ij")
+    return np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1).astype(np.float64)
+
+
+def node_keys(v_units):
+    """Keys of nodes given in lattice units (any shape [..., 3])."""
+    f = np.rint(np.asarray(v_units, dtype=np.float64) * _FINE).astype(np.int64)
+    assert np.all(np.abs(f / _FINE - v_units) == 0), "node off the finest grid"
+    return (f[..., 0] << 42) | (f[..., 1] << 21) | f[..., 2]
+
+
+def nodes_mm(v_units, origin, h):
+    """Node positions as float32 [3, n]: origin + h u in double, rounded once."""
+    u = np.asarray(v_units, dtype=np.float64).reshape(-1, 3)
+    out = np.asarray(origin, dtype=np.float64)[None, :] + float(h) * u
+    return out.T.astype(np.float32)
+
+
+class NodeStore:
+    """Enclosure masks of the labeled nodes, searchable by node key."""
+
+    def __init__(self):
+        self.keys = np.zeros(0, dtype=np.int64)
+        self.masks = np.zeros(0, dtype=np.uint64)
+
+    def add(self, keys, masks):
+        k = np.concatenate([self.keys, keys])
+        m = np.concatenate([self.masks, masks])
+        order = np.argsort(k, kind="stable")
+        self.keys, self.masks = k[order], m[order]
+
+    def missing(self, keys):
+        pos = np.minimum(np.searchsorted(self.keys, keys), max(len(self.keys) - 1, 0))
+        return ~((len(self.keys) > 0) & (self.keys[pos] == keys))
+
+    def get(self, keys):
+        pos = np.searchsorted(self.keys, keys)
+        assert np.all(self.keys[pos] == keys), "node not labeled"
+        return self.masks[pos]
+
+
+def element_masks(keys, store):
+    """AND of the enclosure masks of each tetrahedron's four nodes."""
+    nk = node_keys(vertices_units(keys))                # [n, 4]
+    m = store.get(nk.reshape(-1)).reshape(-1, 4)
+    return m[:, 0] & m[:, 1] & m[:, 2] & m[:, 3]
+
+
+def refine_relabel_nodes(lattice, mask_fn, label_of_mask, rounds):
+    """Section 2.1.3 read literally: the solid-angle test is applied to the
+    nodes (item 1 labels every node of the lattice); a tetrahedron belongs to
+    a surface when all four of its nodes are enclosed, and takes the label of
+    the highest-priority such surface (else 0); then, `rounds` times, every
+    label-boundary leaf is split into its 8 children and only nodes not
+    labeled before are evaluated (item 2).
+    mask_fn(points float32 [3, n]) -> uint64 enclosure masks;
+    label_of_mask(uint64 masks) -> int32 labels.
+
+    Returns (LeafSet, stats) with stats[r] = dict(boundary, children, leaves,
+    nodes = nodes labeled that round)."""
+    store = NodeStore()
+    nodes = lattice_nodes_units(lattice.cells)
+    store.add(node_keys(nodes), mask_fn(nodes_mm(nodes, lattice.origin, lattice.h)))
+    keys = level0_keys(lattice.cells)
+    leaves = LeafSet(keys, label_of_mask(element_masks(keys, store)))
+    stats = [dict(boundary=0, children=0, leaves=len(keys), nodes=len(nodes))]
+    for r in range(1, rounds + 1):
+        bmask = boundary_mask(leaves, lattice.cells, r - 1)
+        bkeys = leaves.keys[bmask]
+        if len(bkeys):
+            lv = decode(bkeys)[0]
+            kids = np.concatenate([children(bkeys[lv == x], lattice.cells).reshape(-1)
+                                   for x in np.unique(lv)])
+        else:
+            kids = np.zeros(0, dtype=np.uint64)
+        n_new = 0
+        if len(kids):
+            v = vertices_units(kids).reshape(-1, 3)
+            nk, first = np.unique(node_keys(v), return_index=True)
+            new = store.missing(nk)
+            n_new = int(new.sum())
+            if n_new:
+                store.add(nk[new], mask_fn(nodes_mm(v[first[new]], lattice.origin, lattice.h)))
+            klab = label_of_mask(element_masks(kids, store))
+        else:
+            klab = np.zeros(0, dtype=np.int32)
+        keep = ~bmask
+        leaves = LeafSet(np.concatenate([leaves.keys[keep], kids]),
+                         np.concatenate([leaves.labels[keep], klab]))
+        stats.append(dict(boundary=int(bmask.sum()), children=int(len(kids)),
+                          leaves=int(len(leaves.keys)), nodes=n_new))
+    return leaves, stats

@@ -350,6 +350,7 @@ struct label_ctx {
     double threshold;
     int32_t *labels;
     double *w_out;
+    uint64_t *mask_out;
 };
 
 static void label_range(void *vctx, int64_t b, int64_t e)
@@ -358,6 +359,7 @@ static void label_range(void *vctx, int64_t b, int64_t e)
     for (int64_t i = b; i < e; ++i) {
         float p[3] = {c->px[i], c->py[i], c->pz[i]};
         int32_t label = 0; /* bounding box */
+        uint64_t mask = 0;
         for (int s = 0; s < c->n_surf; ++s) {
             const float *v = c->verts + 3 * c->vert_off[s];
             const int32_t *t = c->tris + 3 * c->tri_off[s];
@@ -367,10 +369,16 @@ static void label_range(void *vctx, int64_t b, int64_t e)
             if (c->w_out)
                 c->w_out[(int64_t)s * c->n + i] = w;
             /* later surfaces have higher priority: they overwrite */
-            if (on || w >= c->threshold)
-                label = c->surf_label[s];
+            if (on || w >= c->threshold) {
+                if (c->surf_label)
+                    label = c->surf_label[s];
+                mask |= (uint64_t)1 << s;
+            }
         }
-        c->labels[i] = label;
+        if (c->labels)
+            c->labels[i] = label;
+        if (c->mask_out)
+            c->mask_out[i] = mask;
     }
 }
 
@@ -381,7 +389,20 @@ int64_t oracle_label(int64_t n, const float *px, const float *py, const float *p
                      int32_t *labels, double *w_out)
 {
     struct label_ctx c = {px, py, pz, verts, tris, surf_label, vert_off, tri_off,
-                          n_surf, n, threshold, labels, w_out};
+                          n_surf, n, threshold, labels, w_out, NULL};
+    parallel_for(n, n_threads, label_range, &c);
+    return n * (tri_off[n_surf] - tri_off[0]);
+}
+
+int64_t oracle_enclosure(int64_t n, const float *px, const float *py, const float *pz,
+                         int n_surf, const int64_t *vert_off, const int64_t *tri_off,
+                         const float *verts, const int32_t *tris, double threshold,
+                         int n_threads, uint64_t *masks)
+{
+    struct label_ctx c = {px, py, pz, verts, tris, NULL, vert_off, tri_off,
+                          n_surf, n, threshold, NULL, NULL, masks};
+    if (n_surf > 64)
+        return -1;
     parallel_for(n, n_threads, label_range, &c);
     return n * (tri_off[n_surf] - tri_off[0]);
 }

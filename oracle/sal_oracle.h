@@ -61,6 +61,15 @@ int64_t oracle_label(int64_t n, const float *px, const float *py, const float *p
                      const int32_t *surf_label, double threshold, int n_threads,
                      int32_t *labels, double *w_out);
 
+/* Enclosure bits for n points: bit s of masks[i] is set when point i is
+ * enclosed by surface s (w >= threshold, or on the surface), the same test
+ * oracle_label applies.  At most 64 surfaces (else returns -1).  Returns
+ * the number of (point, surface) pairs evaluated. */
+int64_t oracle_enclosure(int64_t n, const float *px, const float *py, const float *pz,
+                         int n_surf, const int64_t *vert_off, const int64_t *tri_off,
+                         const float *verts, const int32_t *tris, double threshold,
+                         int n_threads, uint64_t *masks);
+
 /* Independent inside test for a surface that is star-shaped about `center`:
  * find the face whose cone (center, v0, v1, v2) holds p, then take the exact
  * side of p against that face.  Returns 1 inside, 0 outside, 2 on the surface.

@@ -1,5 +1,7 @@
 """Pins of the lattice / refinement oracle (paper sections 2.1.1-2.1.3) against
 exact integer geometry and brute force."""
+import json
+import os
 from fractions import Fraction
 from itertools import combinations
 
@@ -174,3 +176,75 @@ def test_centroids_in_mm_are_exact_dyadics():
     c = kuhn.centroids_mm(keys, lat.origin, lat.h).astype(np.float64)
     ref = np.array(lat.origin)[:, None] + lat.h * kuhn.centroid_units(keys).T
     assert np.array_equal(c, ref)
+
+
+# ------------------------------------------------- node-based labeling (f1)
+def _ary_surfaces(subdiv=3):
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ary_three_sphere.json")))
+    uv, f = synth.icosphere(subdiv)
+    return [synth.Surface(v=(uv * r).astype(np.float32), f=f.astype(np.int32), label=lab,
+                          center=np.zeros(3))
+            for r, lab in zip(g["radii_mm"], g["labels_outermost_first"])]
+
+
+def _node_run(lattice, surfaces, rounds):
+    return kuhn.refine_relabel_nodes(lattice, lambda p: oracle.enclosure(p, surfaces),
+                                     lambda m: oracle.mask_label(m, surfaces), rounds)
+
+
+def test_node_rule_on_nested_shells_is_the_outermost_vertex_label():
+    """For nested shells (the Ary model) a node's enclosure set is every shell
+    out to its own, so "all four nodes enclosed" gives the vertex label that is
+    least deep in the nesting: here the smallest label id.  Vertex labels come
+    from point labels of the vertices, positions recomputed here."""
+    surfs = _ary_surfaces()
+    lat = synth.Lattice(origin=(-110.0, -110.0, -110.0), h=220.0 / 10, cells=(10, 10, 10))
+    leaves, st = _node_run(lat, surfs, 2)
+    v = kuhn.vertices_units(leaves.keys)                        # [n, 4, 3]
+    pos = (np.asarray(lat.origin)[None, None, :] + lat.h * v).astype(np.float32)
+    vl = oracle.label(np.ascontiguousarray(pos.reshape(-1, 3).T), surfs).reshape(-1, 4)
+    assert np.array_equal(leaves.labels, vl.min(axis=1))
+    assert st[1]["boundary"] > 0 and st[2]["boundary"] > 0
+
+
+def test_node_rule_on_a_sphere_matches_the_exact_radial_test():
+    """Element label 1 exactly when all four nodes are inside the sphere by
+    the exact star-shaped test (no solid angles involved)."""
+    cfg = synth.config_small("sphere", cells=8, subdiv=2)
+    s = cfg.surfaces[0]
+    leaves, _ = _node_run(cfg.lattice, [s], 2)
+    v = kuhn.vertices_units(leaves.keys)
+    pos = (np.asarray(cfg.lattice.origin)[None, None, :] + cfg.lattice.h * v).astype(np.float32)
+    inside = oracle.radial_inside(np.ascontiguousarray(pos.reshape(-1, 3).T), s).reshape(-1, 4) > 0
+    want = np.where(inside.all(axis=1), s.label, 0)
+    assert np.array_equal(leaves.labels, want)
+
+
+def test_node_rule_counts_and_partition():
+    cfg = synth.config_small("head", cells=6, subdiv=2)
+    leaves, st = _node_run(cfg.lattice, cfg.surfaces, 2)
+    n0 = 6 * int(np.prod(cfg.lattice.cells))
+    assert len(leaves.keys) == n0 + 7 * sum(r["boundary"] for r in st)
+    vol = sum(1.0 / 6.0 * 8.0 ** -lv for lv in kuhn.decode(leaves.keys)[0])
+    assert abs(vol - np.prod(cfg.lattice.cells)) < 1e-9
+    # every node of every leaf has been labeled exactly once
+    nk = np.unique(kuhn.node_keys(kuhn.vertices_units(leaves.keys)).reshape(-1))
+    assert sum(r["nodes"] for r in st) >= len(nk)
+
+
+@pytest.mark.parametrize("mutant", ["any_node", "three_nodes"])
+def test_node_pins_catch_a_wrong_element_rule(monkeypatch, mutant):
+    """A plausible mistake in the four-node rule (any node instead of all, or
+    a node dropped) is caught by the pins above."""
+    def any_node(keys, store):
+        m = store.get(kuhn.node_keys(kuhn.vertices_units(keys)).reshape(-1)).reshape(-1, 4)
+        return m[:, 0] | m[:, 1] | m[:, 2] | m[:, 3]
+
+    def three_nodes(keys, store):
+        m = store.get(kuhn.node_keys(kuhn.vertices_units(keys)).reshape(-1)).reshape(-1, 4)
+        return m[:, 0] & m[:, 1] & m[:, 2]
+
+    monkeypatch.setattr(kuhn, "element_masks", {"any_node": any_node,
+                                                "three_nodes": three_nodes}[mutant])
+    with pytest.raises(AssertionError):
+        test_node_rule_on_a_sphere_matches_the_exact_radial_test()
