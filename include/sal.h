@@ -128,6 +128,13 @@ sal_status sal_surface_set_get_info(const sal_surface_set *set, sal_surface_set_
  *                          those of the FP64 form. */
 enum { SAL_PREC_FP64 = 0, SAL_PREC_FP32_RECHECK = 1 };
 enum { SAL_WINDING_NONE = 0, SAL_WINDING_F32 = 1, SAL_WINDING_F64 = 2 };
+/* Element rule of sal_refine_relabel (section 2.1.3):
+ *   SAL_RULE_CENTROID    a tetrahedron takes the label of its centroid;
+ *   SAL_RULE_FOUR_NODES  the solid-angle test is applied to the mesh nodes and
+ *                        a tetrahedron takes the label of the highest-priority
+ *                        surface enclosing all four of its nodes (else 0); a
+ *                        split labels the six edge midpoints of the parent. */
+enum { SAL_RULE_CENTROID = 0, SAL_RULE_FOUR_NODES = 1 };
 
 typedef struct sal_label_options {
     int32_t precision;        /* SAL_PREC_* (default SAL_PREC_FP32_RECHECK) */
@@ -149,8 +156,12 @@ typedef struct sal_label_options {
                                  hipGraph and replay it while the same instances (same
                                  surface sets, pointers, sizes, options) come back;
                                  sal_refine_relabel: 1 = run the rounds as launches of
-                                 one captured round graph (see there);
+                                 one captured round graph (see there; centroid
+                                 rule only, the four-node rule runs host-driven);
                                  sal_label_points ignores it */
+    int32_t element_rule;     /* SAL_RULE_* for sal_refine_relabel; fixed by a mesh's
+                                 first labeling (a later call with another rule
+                                 fails with SAL_ERR_INVALID_ARG) */
 } sal_label_options;
 
 /* Fills the defaults listed above. */

@@ -47,7 +47,8 @@ class LabelOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("winding_type", ctypes.c_int32),
                 ("threshold", ctypes.c_double), ("recheck_band", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("points_per_lane", ctypes.c_int32),
-                ("block_waves", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("block_waves", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("element_rule", ctypes.c_int32)]
 
 
 class LabelStats(ctypes.Structure):
@@ -149,8 +150,11 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+RULE = {"centroid": 0, "four_nodes": 1}
+
+
 def label_options(precision="fp32", winding=None, threshold=0.5, band=1e-3, kappa=0.0,
-                  points_per_lane=0, block_waves=0, use_graph=False):
+                  points_per_lane=0, block_waves=0, use_graph=False, rule="centroid"):
     o = LabelOptions()
     lib().sal_label_options_default(ctypes.byref(o))
     o.precision = PREC[precision]
@@ -161,6 +165,7 @@ def label_options(precision="fp32", winding=None, threshold=0.5, band=1e-3, kapp
     o.points_per_lane = points_per_lane
     o.block_waves = block_waves
     o.use_graph = 1 if use_graph else 0
+    o.element_rule = RULE[rule]
     return o
 
 

@@ -69,13 +69,15 @@ sal_status resolve_options(const sal_label_options *in, sal_label_options *out) 
     if (out->block_waves != 0 && out->block_waves != 1 && out->block_waves != 2 && out->block_waves != 4 &&
         out->block_waves != 8)
         return set_error(SAL_ERR_INVALID_ARG, "block_waves must be 0, 1, 2, 4 or 8");
+    if (out->element_rule != SAL_RULE_CENTROID && out->element_rule != SAL_RULE_FOUR_NODES)
+        return set_error(SAL_ERR_INVALID_ARG, "element_rule must be SAL_RULE_CENTROID or SAL_RULE_FOUR_NODES");
     return SAL_OK;
 }
 
 sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_t n,
                             const int64_t *n_dev, const float *x, const float *y, const float *z,
                             const sal_label_options &opt, int32_t *labels, void *winding,
-                            hipEvent_t ev_mid, hipStream_t stream) {
+                            hipEvent_t ev_mid, hipStream_t stream, unsigned long long *masks) {
     PairloopArgs a{};
     a.rec32 = set->rec32;
     a.rec64 = set->rec64;
@@ -93,6 +95,7 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     a.winding = winding;
     a.winding_type = winding ? opt.winding_type : SAL_WINDING_NONE;
     if (!winding) a.winding = nullptr;
+    a.masks = masks;
     a.flag_list = ctx->flag_list;
     a.counters = ctx->counters;
     if (opt.precision == SAL_PREC_FP64) {
@@ -116,6 +119,7 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     r.labels = labels;
     r.winding = a.winding;
     r.winding_type = a.winding_type;
+    r.masks = masks;
     r.flag_list = ctx->flag_list;
     r.counters = ctx->counters;
     r.n_surf = set->n_surf;
@@ -133,7 +137,7 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
 sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
                          const float *y, const float *z, const sal_label_options &opt_in,
                          int32_t *labels, void *winding, hipEvent_t ev_start, hipEvent_t ev_mid,
-                         int *shape) {
+                         int *shape, unsigned long long *masks) {
     sal_label_options opt = opt_in;
     sal_status ts = tune_launch(ctx, set, n, x, y, z, labels, &opt);
     if (ts != SAL_OK) return ts;
@@ -143,7 +147,7 @@ sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n
         shape[1] = opt.block_waves;
     }
     return enqueue_label_on(ctx, set, n, nullptr, x, y, z, opt, labels, winding, ev_mid,
-                            ctx->stream);
+                            ctx->stream, masks);
 }
 
 }  // namespace sal
@@ -194,6 +198,7 @@ void sal_label_options_default(sal_label_options *o) {
     o->points_per_lane = 0;
     o->block_waves = 0;
     o->use_graph = 0;
+    o->element_rule = SAL_RULE_CENTROID;
 }
 
 sal_status sal_context_create(int device, void *stream, sal_context **out) {

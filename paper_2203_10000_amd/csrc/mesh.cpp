@@ -70,6 +70,13 @@ struct sal_tet_mesh {
     sal::RoundState *rs = nullptr;
     hipGraphExec_t round_graph = nullptr;
     uint64_t round_key = 0;
+    // four-node rule: level-0 node grid masks, per-leaf vertex masks of
+    // levels >= 1, masks of the labeled midpoints
+    int rule = -1;   // element rule fixed by the first labeling
+    unsigned long long *node0 = nullptr;
+    unsigned long long *vmask[sal::kMaxLevels + 1] = {};
+    unsigned long long *mid_masks = nullptr;
+    int64_t mid_cap = 0;
 };
 
 namespace sal {
@@ -110,6 +117,9 @@ sal_status ensure_level(sal_tet_mesh *m, int l, int64_t need, hipStream_t s) {
     if ((st = grow(&m->label[l], m->n[l], cap, s)) != SAL_OK) return st;
     if ((st = grow(&m->child[l], m->n[l], cap, s)) != SAL_OK) return st;
     if ((st = grow(&m->flag[l], 0, cap, s)) != SAL_OK) return st;
+    if (l > 0 && m->rule == SAL_RULE_FOUR_NODES &&
+        (st = grow(&m->vmask[l], 4 * m->n[l], 4 * cap, s)) != SAL_OK)
+        return st;
     m->cap[l] = cap;
     return SAL_OK;
 }
@@ -149,7 +159,7 @@ sal_status compact(sal_tet_mesh *m, const CompactSrc &src, int64_t n, int32_t *o
 // (before the recheck).
 sal_status label_scratch(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set, int64_t n,
                          const sal_label_options &opt, int32_t *labels, hipEvent_t ev_start,
-                         hipEvent_t ev_mid) {
+                         hipEvent_t ev_mid, unsigned long long *masks = nullptr) {
     if (n <= 0) return SAL_OK;
     if (opt.precision == SAL_PREC_FP32_RECHECK) {
         sal_status st = ensure_flag_capacity(ctx, n);
@@ -157,7 +167,7 @@ sal_status label_scratch(sal_context *ctx, sal_tet_mesh *m, const sal_surface_se
     }
     SAL_HIP(launch_fill_u64(ctx->counters + kCntFlagged, 0ull, 1, ctx->stream));
     return enqueue_label(ctx, set, n, m->cen[0], m->cen[1], m->cen[2], opt, labels, nullptr,
-                         ev_start, ev_mid);
+                         ev_start, ev_mid, nullptr, masks);
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -202,18 +212,35 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
     for (int l = top; l >= 0; --l) {
         if (count[l] == 0) continue;
         const int64_t kids = 8 * count[l];
+        const bool nodes = m->rule == SAL_RULE_FOUR_NODES;
+        const int64_t n_pts = nodes ? 6 * count[l] : kids;   // midpoints or centroids
         if ((st = ensure_level(m, l + 1, m->n[l + 1] + kids, s)) != SAL_OK) return st;
-        if ((st = ensure_centroids(m, kids, s)) != SAL_OK) return st;
+        if ((st = ensure_centroids(m, n_pts, s)) != SAL_OK) return st;
+        if (nodes && ((st = ensure_buf(&m->lab_scratch, &m->lab_cap, n_pts, s)) != SAL_OK ||
+                      (st = ensure_buf(&m->mid_masks, &m->mid_cap, n_pts, s)) != SAL_OK))
+            return st;
         const int64_t base_block = m->n[l + 1] / 8;
         LevelPtrs L2 = ptrs(m);
         SAL_HIP(hipEventRecord(m->ev[5], s));
-        SAL_HIP(launch_split(L2, m->g, m->T, l, m->list + off[l], count[l], base_block, m->cen[0],
-                             m->cen[1], m->cen[2], s));
+        SAL_HIP(launch_split(L2, m->g, m->T, l, m->list + off[l], count[l], base_block,
+                             nodes ? nullptr : m->cen[0], nodes ? nullptr : m->cen[1],
+                             nodes ? nullptr : m->cen[2], s));
+        if (nodes)
+            SAL_HIP(launch_midpoints(L2, m->g, l, m->list + off[l], count[l], m->cen[0], m->cen[1],
+                                     m->cen[2], s));
         SAL_HIP(hipEventRecord(m->ev[6], s));
         m->n[l + 1] += kids;
-        if ((st = label_scratch(ctx, m, set, kids, opt, m->label[l + 1] + 8 * base_block,
-                                m->ev[10], m->ev[9])) != SAL_OK)
+        if (nodes) {
+            if ((st = label_scratch(ctx, m, set, n_pts, opt, m->lab_scratch, m->ev[10], m->ev[9],
+                                    m->mid_masks)) != SAL_OK)
+                return st;
+            SAL_HIP(launch_child_masks(L2, m->g, l, m->list + off[l], count[l], base_block,
+                                       m->node0, m->vmask[l], m->mid_masks, m->vmask[l + 1],
+                                       set->surf, s));
+        } else if ((st = label_scratch(ctx, m, set, kids, opt, m->label[l + 1] + 8 * base_block,
+                                       m->ev[10], m->ev[9])) != SAL_OK) {
             return st;
+        }
         SAL_HIP(hipEventRecord(m->ev[7], s));
         SAL_HIP(hipEventSynchronize(m->ev[7]));
         ms_split += elapsed(m->ev[5], m->ev[6]);
@@ -221,7 +248,7 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
         ms_recheck += elapsed(m->ev[9], m->ev[7]);
         if (l + 1 > m->max_level) m->max_level = l + 1;
         n_split += count[l];
-        n_label += kids;
+        n_label += n_pts;
     }
     m->n_leaves += 7 * n_split;
     SAL_HIP(hipEventRecord(m->ev[8], s));
@@ -472,6 +499,10 @@ void sal_tet_mesh_destroy(sal_tet_mesh *m) {
     if (m->blocks) (void)hipFree(m->blocks);
     if (m->totals) (void)hipFree(m->totals);
     if (m->lab_scratch) (void)hipFree(m->lab_scratch);
+    if (m->node0) (void)hipFree(m->node0);
+    for (auto *v : m->vmask)
+        if (v) (void)hipFree(v);
+    if (m->mid_masks) (void)hipFree(m->mid_masks);
     if (m->rs) (void)hipFree(m->rs);
     if (m->round_graph) (void)hipGraphExecDestroy(m->round_graph);
     for (auto &e : m->ev)
@@ -552,7 +583,28 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
         SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, s));
         SAL_HIP(hipEventRecord(m->ev[0], s));
         int64_t labeled0 = 0;
-        if (!m->labeled0) {
+        if (m->labeled0 && m->rule != opt.element_rule)
+            return set_error(SAL_ERR_INVALID_ARG, "the mesh was labeled with another element rule");
+        if (!m->labeled0 && opt.element_rule == SAL_RULE_FOUR_NODES) {
+            // item 1 read literally: every node of the lattice, then each
+            // tetrahedron from its four nodes
+            m->rule = SAL_RULE_FOUR_NODES;
+            const int64_t n_nodes = (int64_t)(m->g.cells[0] + 1) * (m->g.cells[1] + 1) *
+                                    (int64_t)(m->g.cells[2] + 1);
+            if ((st = ensure_centroids(m, n_nodes, s)) != SAL_OK) return st;
+            if ((st = ensure_buf(&m->lab_scratch, &m->lab_cap, n_nodes, s)) != SAL_OK) return st;
+            if (!m->node0 && hipMalloc((void **)&m->node0, (size_t)n_nodes * sizeof(uint64_t)) !=
+                                 hipSuccess)
+                return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(node masks)");
+            SAL_HIP(launch_lattice_nodes(m->g, n_nodes, m->cen[0], m->cen[1], m->cen[2], s));
+            if ((st = label_scratch(ctx, m, set, n_nodes, opt, m->lab_scratch, m->ev[10],
+                                    m->ev[9], m->node0)) != SAL_OK)
+                return st;
+            SAL_HIP(launch_elem_from_nodes0(m->g, m->n[0], m->node0, set->surf, m->label[0], s));
+            m->labeled0 = true;
+            labeled0 = n_nodes;
+        } else if (!m->labeled0) {
+            m->rule = SAL_RULE_CENTROID;
             if ((st = ensure_centroids(m, m->n[0], s)) != SAL_OK) return st;
             SAL_HIP(launch_lattice_centroids(m->g, m->n[0], m->cen[0], m->cen[1], m->cen[2], s));
             if ((st = label_scratch(ctx, m, set, m->n[0], opt, m->label[0], m->ev[10],
@@ -579,7 +631,7 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
         }
 
         int first = 1;
-        if (opt.use_graph && rounds > 0) {
+        if (opt.use_graph && rounds > 0 && m->rule == SAL_RULE_CENTROID) {
             int done = 0;
             st = graph_rounds(ctx, m, set, opt, rounds, per_round ? per_round + 1 : nullptr, &done);
             if (st != SAL_OK) return st;

@@ -295,7 +295,7 @@ __device__ void split_one(const LevelPtrs &L, const LatticeGeom &g, const ChildT
     L.key[l + 1][o] = make_key(l + 1, cq, cc[0], cc[1], cc[2]);
     L.child[l + 1][o] = -1;
     L.label[l + 1][o] = -2;
-    centroid(g, l + 1, cq, cc, cx[jj], cy[jj], cz[jj]);
+    if (cx) centroid(g, l + 1, cq, cc, cx[jj], cy[jj], cz[jj]);
 }
 
 __global__ void k_split(LevelPtrs L, LatticeGeom g, ChildTables T, int l,
@@ -304,6 +304,137 @@ __global__ void k_split(LevelPtrs L, LatticeGeom g, ChildTables T, int l,
     const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (jj >= count * 8) return;
     split_one(L, g, T, l, list, jj, base_block, cx, cy, cz);
+}
+
+// ------------------------------------------------------- four-node rule
+// Section 2.1.3 as printed: the solid-angle test is applied to the nodes, and
+// a tetrahedron belongs to a surface when all four of its nodes are enclosed.
+// Node enclosure masks: level-0 nodes in a dense (nx+1)(ny+1)(nz+1) grid,
+// nodes added by a split (edge midpoints) carried per child tetrahedron as
+// the masks of its four vertices (x0..x3 in its own Kuhn order).
+
+// Vertices x0..x3 of (cell c, permutation q) in that level's integer units.
+__device__ __forceinline__ void kuhn_vertices(int q, const int64_t c[3], int64_t X[4][3]) {
+    int p0, p1, p2;
+    perm_of(q, p0, p1, p2);
+    for (int a = 0; a < 3; ++a) {
+        X[0][a] = c[a];
+        X[3][a] = c[a] + 1;
+    }
+    for (int a = 0; a < 3; ++a) X[1][a] = X[0][a];
+    X[1][p0] += 1;
+    for (int a = 0; a < 3; ++a) X[2][a] = X[1][a];
+    X[2][p1] += 1;
+}
+
+__device__ __forceinline__ int32_t mask_label(const SurfaceDev *surf, uint64_t m) {
+    return m ? surf[63 - __builtin_clzll(m)].label : 0;
+}
+
+__global__ void k_lattice_nodes(LatticeGeom g, int64_t n_nodes, float *__restrict__ x,
+                                float *__restrict__ y, float *__restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    const int64_t nx1 = g.cells[0] + 1, ny1 = g.cells[1] + 1;
+    const int64_t u = i % nx1, v = (i / nx1) % ny1, w = i / (nx1 * ny1);
+    x[i] = (float)__dadd_rn(g.origin[0], __dmul_rn(g.h, (double)u));
+    y[i] = (float)__dadd_rn(g.origin[1], __dmul_rn(g.h, (double)v));
+    z[i] = (float)__dadd_rn(g.origin[2], __dmul_rn(g.h, (double)w));
+}
+
+__device__ __forceinline__ int64_t node0_index(const LatticeGeom &g, const int64_t X[3]) {
+    return (X[2] * (g.cells[1] + 1) + X[1]) * (int64_t)(g.cells[0] + 1) + X[0];
+}
+
+// Level-0 labels from the node grid.
+__global__ void k_elem_from_nodes0(LatticeGeom g, int64_t n0,
+                                   const unsigned long long *__restrict__ node0,
+                                   const SurfaceDev *__restrict__ surf,
+                                   int32_t *__restrict__ label0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n0) return;
+    const int q = (int)(i % 6);
+    int64_t cell = i / 6;
+    int64_t c[3];
+    c[0] = cell % g.cells[0];
+    cell /= g.cells[0];
+    c[1] = cell % g.cells[1];
+    c[2] = cell / g.cells[1];
+    int64_t X[4][3];
+    kuhn_vertices(q, c, X);
+    uint64_t m = ~0ull;
+    for (int v = 0; v < 4; ++v) m &= node0[node0_index(g, X[v])];
+    label0[i] = mask_label(surf, m);
+}
+
+// The six edge midpoints of every listed level-l leaf (edges 01, 02, 03, 12,
+// 13, 23), in millimetres, into the labeling scratch: origin + h 2^-(l+1)
+// (X_a + X_b), products and sums rounded once in double, then to float.
+__global__ void k_midpoints(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
+                            int64_t count, float *__restrict__ mx, float *__restrict__ my,
+                            float *__restrict__ mz) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= count * 6) return;
+    const int64_t j = jj / 6;
+    const int e = (int)(jj - j * 6);
+    int q, lk;
+    int64_t c[3];
+    split_key(entry_key(L, g, l, list[j]), lk, q, c);
+    int64_t X[4][3];
+    kuhn_vertices(q, c, X);
+    const int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+    const double hl = ldexp(g.h, -(l + 1));
+    float *out[3] = {mx, my, mz};
+    for (int a = 0; a < 3; ++a)
+        out[a][jj] = (float)__dadd_rn(g.origin[a], __dmul_rn(hl, (double)(X[ea[e]][a] + X[eb[e]][a])));
+}
+
+// Vertex masks and labels of the 8 children of every listed level-l leaf:
+// each child vertex is one of the parent's 10 nodes at level l + 1 (2 X_i, or
+// X_a + X_b for an edge), matched by integer coordinates.
+__global__ void k_child_masks(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
+                              int64_t count, int64_t base_block,
+                              const unsigned long long *__restrict__ node0,
+                              const unsigned long long *__restrict__ vmask_parent,
+                              const unsigned long long *__restrict__ mid_masks,
+                              unsigned long long *__restrict__ vmask_child,
+                              const SurfaceDev *__restrict__ surf) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= count * 8) return;
+    const int64_t j = jj >> 3;
+    const int r = (int)(jj & 7);
+    const int64_t i = list[j];
+    int q, lk;
+    int64_t c[3];
+    split_key(entry_key(L, g, l, i), lk, q, c);
+    int64_t X[4][3];
+    kuhn_vertices(q, c, X);
+    int64_t N[10][3];
+    uint64_t M[10];
+    for (int v = 0; v < 4; ++v) {
+        for (int a = 0; a < 3; ++a) N[v][a] = 2 * X[v][a];
+        M[v] = l == 0 ? node0[node0_index(g, X[v])] : vmask_parent[4 * i + v];
+    }
+    const int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+    for (int e = 0; e < 6; ++e) {
+        for (int a = 0; a < 3; ++a) N[4 + e][a] = X[ea[e]][a] + X[eb[e]][a];
+        M[4 + e] = mid_masks[6 * j + e];
+    }
+    const int64_t o = 8 * (base_block + j) + r;
+    int cq, clk;
+    int64_t cc[3];
+    split_key(L.key[l + 1][o], clk, cq, cc);
+    int64_t Y[4][3];
+    kuhn_vertices(cq, cc, Y);
+    uint64_t all = ~0ull;
+    for (int v = 0; v < 4; ++v) {
+        uint64_t mv = 0;
+        for (int n = 0; n < 10; ++n)
+            if (N[n][0] == Y[v][0] && N[n][1] == Y[v][1] && N[n][2] == Y[v][2]) mv = M[n];
+        vmask_child[4 * o + v] = mv;
+        all &= mv;
+    }
+    L.label[l + 1][o] = mask_label(surf, all);
 }
 
 // ------------------------------------------------- captured refine round
@@ -425,6 +556,42 @@ __global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 }  // namespace
+
+hipError_t launch_lattice_nodes(const LatticeGeom &g, int64_t n_nodes, float *x, float *y, float *z,
+                               hipStream_t s) {
+    if (n_nodes <= 0) return hipSuccess;
+    k_lattice_nodes<<<grid_for(n_nodes, 256), 256, 0, s>>>(g, n_nodes, x, y, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_elem_from_nodes0(const LatticeGeom &g, int64_t n0,
+                                   const unsigned long long *node0, const SurfaceDev *surf,
+                                   int32_t *label0, hipStream_t s) {
+    if (n0 <= 0) return hipSuccess;
+    k_elem_from_nodes0<<<grid_for(n0, 256), 256, 0, s>>>(g, n0, node0, surf, label0);
+    return hipGetLastError();
+}
+
+hipError_t launch_midpoints(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
+                            int64_t count, float *mx, float *my, float *mz, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_midpoints<<<grid_for(count * 6, 256), 256, 0, s>>>(L, g, l, list, count, mx, my, mz);
+    return hipGetLastError();
+}
+
+hipError_t launch_child_masks(const LevelPtrs &L, const LatticeGeom &g, int l,
+                              const int32_t *list, int64_t count, int64_t base_block,
+                              const unsigned long long *node0,
+                              const unsigned long long *vmask_parent,
+                              const unsigned long long *mid_masks,
+                              unsigned long long *vmask_child, const SurfaceDev *surf,
+                              hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_child_masks<<<grid_for(count * 8, 256), 256, 0, s>>>(L, g, l, list, count, base_block, node0,
+                                                          vmask_parent, mid_masks, vmask_child,
+                                                          surf);
+    return hipGetLastError();
+}
 
 hipError_t launch_lattice_centroids(const LatticeGeom &g, int64_t n0, float *cx, float *cy,
                                     float *cz, hipStream_t s) {

@@ -89,6 +89,22 @@ hipError_t launch_commit(const RoundState *rs, const int64_t *totals, int l,
                          const int32_t *scratch_labels, int32_t *level_labels, hipStream_t s);
 hipError_t launch_round_end(RoundState *rs, const unsigned long long *counters, hipStream_t s);
 
+// Four-node rule (node enclosure masks).
+hipError_t launch_lattice_nodes(const LatticeGeom &g, int64_t n_nodes, float *x, float *y, float *z,
+                               hipStream_t s);
+hipError_t launch_elem_from_nodes0(const LatticeGeom &g, int64_t n0,
+                                   const unsigned long long *node0, const SurfaceDev *surf,
+                                   int32_t *label0, hipStream_t s);
+hipError_t launch_midpoints(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
+                            int64_t count, float *mx, float *my, float *mz, hipStream_t s);
+hipError_t launch_child_masks(const LevelPtrs &L, const LatticeGeom &g, int l,
+                              const int32_t *list, int64_t count, int64_t base_block,
+                              const unsigned long long *node0,
+                              const unsigned long long *vmask_parent,
+                              const unsigned long long *mid_masks,
+                              unsigned long long *vmask_child, const SurfaceDev *surf,
+                              hipStream_t s);
+
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 

@@ -85,6 +85,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         if (valid[j]) a.labels[idx[j]] = good[j] ? lab[j] : -1;
+        if (a.masks && valid[j]) a.masks[idx[j]] = good[j] ? enc[j] : 0ull;
         append_flag(a, good[j] && flg[j] != 0, idx[j], enc[j], flg[j]);
     }
     if (lane == 0) {
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
     const float praw[3] = {fx, fy, fz};
     const double p[3] = {fx, fy, fz};
     int32_t lab = 0;
+    uint64_t enc = 0;
     unsigned n_exact = 0;
     const CRec64 *rec = (const CRec64 *)a.rec64;
     const CSurf *surf = (const CSurf *)a.surf;
@@ -132,7 +134,10 @@ __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
             r += m + 1;
         }
         const double w = S * kInv2Pi;
-        if (on || w >= a.threshold) lab = surf[k].label;
+        if (on || w >= a.threshold) {
+            lab = surf[k].label;
+            enc |= 1ull << k;
+        }
         if (a.winding && valid) {
             const int64_t o = (int64_t)k * n + i;
             const double wv = good ? w : __builtin_nan("");
@@ -141,6 +146,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
         }
     }
     if (valid) a.labels[i] = good ? lab : -1;
+    if (a.masks && valid) a.masks[i] = good ? enc : 0ull;
     const uint64_t any = ballot(n_exact != 0);
     if (any) atomicAdd(&a.counters[kCntExact], (unsigned long long)n_exact);
 }

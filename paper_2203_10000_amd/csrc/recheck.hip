@@ -267,6 +267,7 @@ __global__ void k_rc_entry_final(RecheckArgs a) {
         const FlagEntry e = a.flag_list[i];
         const unsigned long long enc = a.res[i];
         a.labels[e.idx] = enc ? a.surf[63 - __builtin_clzll(enc)].label : 0;
+        if (a.masks) a.masks[e.idx] = enc;
         pairs += (unsigned long long)__popcll(e.flg);
     }
     if (pairs) atomicAdd(&a.counters[kCntRecheck], pairs);
@@ -321,6 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_recheck_f64(RecheckArgs a) {
             // Section 2.1: the enclosing surface latest in the list wins; 0 = box.
             const int32_t lab = enc ? a.surf[63 - __builtin_clzll(enc)].label : 0;
             a.labels[e.idx] = lab;
+            if (a.masks) a.masks[e.idx] = enc;
             atomicAdd(&a.counters[kCntRecheck], (unsigned long long)__popcll(e.flg));
         }
     }

@@ -73,7 +73,8 @@ sal_status resolve_options(const sal_label_options *in, sal_label_options *out);
 sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n, const float *x,
                          const float *y, const float *z, const sal_label_options &opt,
                          int32_t *labels, void *winding, hipEvent_t ev_start,
-                         hipEvent_t ev_after_pairloop, int *shape = nullptr);
+                         hipEvent_t ev_after_pairloop, int *shape = nullptr,
+                         unsigned long long *masks = nullptr);
 
 // The launches of one labeling pass with a resolved launch shape, on
 // `stream`.  With n_dev set the point count is read on the device and n is the
@@ -81,7 +82,8 @@ sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n
 sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_t n,
                             const int64_t *n_dev, const float *x, const float *y, const float *z,
                             const sal_label_options &opt, int32_t *labels, void *winding,
-                            hipEvent_t ev_mid, hipStream_t stream);
+                            hipEvent_t ev_mid, hipStream_t stream,
+                            unsigned long long *masks = nullptr);
 
 // Resolves points_per_lane / block_waves left at 0 by timing the candidates
 // on a prefix of the points against a prefix of the strips (the tuner table

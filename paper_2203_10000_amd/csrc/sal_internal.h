@@ -93,6 +93,7 @@ struct PairloopArgs {
     int32_t *__restrict__ labels;
     void *__restrict__ winding;   // [n_surf][n] float or double, or null
     int winding_type;
+    unsigned long long *__restrict__ masks;  // [n] enclosure bits per point, or null
     FlagEntry *__restrict__ flag_list;  // capacity n
     unsigned long long *__restrict__ counters;
 };
@@ -132,6 +133,7 @@ struct RecheckArgs {
     int32_t *__restrict__ labels;
     void *__restrict__ winding;
     int winding_type;
+    unsigned long long *__restrict__ masks;  // [n] enclosure bits per point, or null
     const FlagEntry *__restrict__ flag_list;
     unsigned long long *__restrict__ counters;
     int n_surf;

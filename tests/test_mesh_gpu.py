@@ -137,3 +137,62 @@ def test_c2_full_size_sampled(ctx):
     want = oracle.label(np.ascontiguousarray(cen[:, idx]), cfg.surfaces)
     assert np.array_equal(labels[idx], want)
     assert st[0]["n_recheck_pairs"] < 0.01 * len(keys)
+
+
+# ------------------------------------------------------- four-node rule
+@pytest.fixture(scope="module")
+def node_oracle():
+    cfg = synth.config_small("head", cells=12, subdiv=3)
+    leaves, st = kuhn.refine_relabel_nodes(
+        cfg.lattice, lambda p: oracle.enclosure(p, cfg.surfaces),
+        lambda m: oracle.mask_label(m, cfg.surfaces), 2)
+    return cfg, leaves, st
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_four_node_rule_two_rounds(ctx, node_oracle, precision):
+    """Section 2.1.3 read literally: nodes labeled, a tetrahedron enclosed by
+    a surface when its four nodes are, new nodes only after each split."""
+    cfg, leaves, ost = node_oracle
+    lat = cfg.lattice
+    mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    st = mesh.refine_relabel(ss, 2, precision=precision, rule="four_nodes")
+    keys, labels, _ = export_np(mesh)
+    order = np.argsort(keys)
+    assert np.array_equal(keys[order], leaves.keys)
+    assert np.array_equal(labels[order], leaves.labels)
+    n_nodes = (lat.cells[0] + 1) * (lat.cells[1] + 1) * (lat.cells[2] + 1)
+    assert st[0]["n_labeled"] == n_nodes
+    for r in (1, 2):
+        assert st[r]["n_boundary"] == ost[r]["boundary"]
+        assert st[r]["n_leaves"] == ost[r]["leaves"]
+        assert st[r]["n_labeled"] == 6 * ost[r]["boundary"]   # six midpoints per split
+
+
+def test_four_node_rule_asked_for_a_graph_runs_host_driven(ctx, node_oracle):
+    cfg, leaves, _ = node_oracle
+    lat = cfg.lattice
+    mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    st = mesh.refine_relabel(ss, 2, rule="four_nodes", use_graph=True)
+    assert all(s["graph"] == 0 for s in st)
+    keys, labels, _ = export_np(mesh)
+    order = np.argsort(keys)
+    assert np.array_equal(keys[order], leaves.keys)
+    assert np.array_equal(labels[order], leaves.labels)
+
+
+def test_element_rule_is_fixed_by_the_first_labeling(ctx):
+    cfg = synth.config_small("sphere", cells=6, subdiv=2)
+    lat = cfg.lattice
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    mesh.refine_relabel(ss, 1)
+    with pytest.raises(sal.SalError) as e:
+        mesh.refine_relabel(ss, 1, rule="four_nodes")
+    assert e.value.status == 1
+    other = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    other.refine_relabel(ss, 1, rule="four_nodes")
+    other.refine_relabel(ss, 1, rule="four_nodes")
+    assert other.size()[1] == 2
