@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2 (default, the benchmark line); c3 refine-and-relabel, c4 batched, "
                          "c5 precision stress: measurement lines for the design notes")
+    ap.add_argument("--rule", default="centroid", choices=["centroid", "four_nodes"],
+                    help="element rule of the c3 refine-and-relabel run")
     ap.add_argument("--c5-lattice-fraction", type=float, default=0.125,
                     help="c5: fraction of the 0.5 mm lattice (a slab along z) to label")
     ap.add_argument("--check-sample", type=int, default=20000,
@@ -150,6 +152,32 @@ def _oracle_check(pts_np, surfaces, gpu_labels_np, n, rng, near_mask=None):
 _ORACLE_RATE = {}
 
 
+def _oracle_check_nodes(keys, lat, surfaces, gpu_labels_np, n, rng, near_mask=None):
+    """Four-node rule: a sample of leaves, each labeled by the oracle from the
+    enclosure masks of its four nodes."""
+    import numpy as np
+    import oracle
+    from oracle import kuhn
+    progress("oracle check of %d (+%d near) leaves, four-node rule" %
+             (n, n if near_mask is not None else 0))
+    idx = rng.choice(len(keys), min(n, len(keys)), replace=False)
+    if near_mask is not None and near_mask.any():
+        near = np.nonzero(near_mask)[0]
+        idx = np.unique(np.concatenate([idx, rng.choice(near, min(n, len(near)), replace=False)]))
+    v = kuhn.vertices_units(keys[idx]).reshape(-1, 3)
+    pts = kuhn.nodes_mm(v, lat.origin, lat.h)
+    threads = oracle.host_threads()
+    t0 = time.perf_counter()
+    m = oracle.enclosure(pts, surfaces, n_threads=threads).reshape(-1, 4)
+    dt = time.perf_counter() - t0
+    want = oracle.mask_label(m[:, 0] & m[:, 1] & m[:, 2] & m[:, 3], surfaces)
+    n_tri = sum(len(s.f) for s in surfaces)
+    _ORACLE_RATE.update({"value": pts.shape[1] * n_tri / max(dt, 1e-9) / 1e9, "unit": "G pairs/s",
+                         "cores": threads, "kind": "oracle",
+                         "sample": "%d nodes x %d triangles, %.1f s" % (pts.shape[1], n_tri, dt)})
+    return int((gpu_labels_np[idx] != want).sum()), int(len(idx))
+
+
 def run_c3(args):
     """c3: 20 compartments (4 x 81,920 + 16 x 5,120 triangles), 1 mm lattice
     (48M centroids), two refine-and-relabel rounds in FP32 + recheck."""
@@ -166,20 +194,26 @@ def run_c3(args):
     mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = mesh.refine_relabel(ss, cfg.rounds, precision="fp32")
+    st = mesh.refine_relabel(ss, cfg.rounds, precision="fp32", rule=args.rule)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pairs = sum(r["n_pairs"] for r in st)
     n_leaves, lv = mesh.size()
-    e = mesh.export(keys=False, labels=True, centroids=True)
+    e = mesh.export(keys=args.rule == "four_nodes", labels=True, centroids=True)
     lab = e["labels"].cpu().numpy()
     cen = e["centroids"].cpu().numpy()
+    keys = e["keys"].cpu().numpy().view(np.uint64) if e["keys"] is not None else None
     del e
     rng = np.random.default_rng(33)
     r = np.linalg.norm(cen.astype(np.float64), axis=0)
     near = np.min(np.abs(r[:, None] - np.array([92, 86, 80, 76.0])), axis=1) < 4.0
-    mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, near)
-    return {"workload": "c3", "triangles": cfg.n_tri, "rounds": st, "leaves": n_leaves,
+    if args.rule == "four_nodes":
+        mism, checked = _oracle_check_nodes(keys, lat, cfg.surfaces, lab, args.check_sample, rng,
+                                            near)
+    else:
+        mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, near)
+    return {"workload": "c3", "rule": args.rule, "triangles": cfg.n_tri, "rounds": st,
+            "leaves": n_leaves,
             "max_level": lv, "pairs": pairs, "wall_s": wall,
             "g_pairs_per_s": pairs / wall / 1e9,
             "leaf_count_identity": n_leaves == lat.n_points + 7 * sum(x["n_boundary"] for x in st),
