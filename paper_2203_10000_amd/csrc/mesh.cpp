@@ -77,6 +77,20 @@ struct sal_tet_mesh {
     unsigned long long *vmask[sal::kMaxLevels + 1] = {};
     unsigned long long *mid_masks = nullptr;
     int64_t mid_cap = 0;
+    // midpoints of a split level and the node table (each node labeled once)
+    float *mid_xyz[3] = {};
+    int64_t mid_xyz_cap = 0;
+    uint64_t *mid_key = nullptr;
+    int64_t mid_key_cap = 0;
+    int64_t *mid_slot = nullptr;
+    int64_t mid_slot_cap = 0;
+    int32_t *new_list = nullptr;
+    int64_t new_list_cap = 0;
+    unsigned long long *new_masks = nullptr;
+    int64_t new_masks_cap = 0;
+    unsigned long long *n_new = nullptr;
+    unsigned long long *tkeys = nullptr, *tmasks = nullptr;
+    int64_t tcap = 0, tused = 0;   // tused: upper bound of the entries
 };
 
 namespace sal {
@@ -170,6 +184,48 @@ sal_status label_scratch(sal_context *ctx, sal_tet_mesh *m, const sal_surface_se
                          ev_start, ev_mid, nullptr, masks);
 }
 
+// As label_scratch, for a point count held on the device (capacity n_cap).
+sal_status label_scratch_dev(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
+                             int64_t n_cap, const unsigned long long *n_dev,
+                             const sal_label_options &opt_in, int32_t *labels, hipEvent_t ev_start,
+                             hipEvent_t ev_mid, unsigned long long *masks) {
+    if (n_cap <= 0) return SAL_OK;
+    if (opt_in.precision == SAL_PREC_FP32_RECHECK) {
+        sal_status st = ensure_flag_capacity(ctx, n_cap);
+        if (st != SAL_OK) return st;
+    }
+    SAL_HIP(launch_fill_u64(ctx->counters + kCntFlagged, 0ull, 1, ctx->stream));
+    sal_label_options opt = opt_in;
+    sal_status st = tune_launch(ctx, set, n_cap, m->cen[0], m->cen[1], m->cen[2], labels, &opt);
+    if (st != SAL_OK) return st;
+    SAL_HIP(hipEventRecord(ev_start, ctx->stream));
+    return enqueue_label_on(ctx, set, n_cap, (const int64_t *)n_dev, m->cen[0], m->cen[1],
+                            m->cen[2], opt, labels, nullptr, ev_mid, ctx->stream, masks);
+}
+
+// Room in the node table for `more` entries (kept at most half full; a
+// larger table is filled by re-inserting the old entries).
+sal_status ensure_node_table(sal_tet_mesh *m, int64_t more, hipStream_t s) {
+    const int64_t need = 2 * (m->tused + more);
+    if (need <= m->tcap) return SAL_OK;
+    int64_t cap = 1 << 16;
+    while (cap < need) cap <<= 1;
+    unsigned long long *k = nullptr, *v = nullptr;
+    SAL_HIP(hipMalloc((void **)&k, (size_t)cap * sizeof(unsigned long long)));
+    SAL_HIP(hipMalloc((void **)&v, (size_t)cap * sizeof(unsigned long long)));
+    SAL_HIP(launch_fill_u64(k, ~0ull, cap, s));
+    if (m->tkeys) {
+        SAL_HIP(launch_node_rehash(m->tkeys, m->tmasks, m->tcap, k, v, cap, s));
+        SAL_HIP(hipStreamSynchronize(s));
+        SAL_HIP(hipFree(m->tkeys));
+        SAL_HIP(hipFree(m->tmasks));
+    }
+    m->tkeys = k;
+    m->tmasks = v;
+    m->tcap = cap;
+    return SAL_OK;
+}
+
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0f;
@@ -216,24 +272,50 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
         const int64_t n_pts = nodes ? 6 * count[l] : kids;   // midpoints or centroids
         if ((st = ensure_level(m, l + 1, m->n[l + 1] + kids, s)) != SAL_OK) return st;
         if ((st = ensure_centroids(m, n_pts, s)) != SAL_OK) return st;
-        if (nodes && ((st = ensure_buf(&m->lab_scratch, &m->lab_cap, n_pts, s)) != SAL_OK ||
-                      (st = ensure_buf(&m->mid_masks, &m->mid_cap, n_pts, s)) != SAL_OK))
-            return st;
+        if (nodes) {
+            int64_t c3 = m->mid_xyz_cap;
+            for (int a = 0; a < 3; ++a) {
+                c3 = m->mid_xyz_cap;
+                if ((st = ensure_buf(&m->mid_xyz[a], &c3, n_pts, s)) != SAL_OK) return st;
+            }
+            m->mid_xyz_cap = c3;
+            if ((st = ensure_buf(&m->lab_scratch, &m->lab_cap, n_pts, s)) != SAL_OK ||
+                (st = ensure_buf(&m->mid_masks, &m->mid_cap, n_pts, s)) != SAL_OK ||
+                (st = ensure_buf(&m->mid_key, &m->mid_key_cap, n_pts, s)) != SAL_OK ||
+                (st = ensure_buf(&m->mid_slot, &m->mid_slot_cap, n_pts, s)) != SAL_OK ||
+                (st = ensure_buf(&m->new_list, &m->new_list_cap, n_pts, s)) != SAL_OK ||
+                (st = ensure_buf(&m->new_masks, &m->new_masks_cap, n_pts, s)) != SAL_OK ||
+                (st = ensure_node_table(m, n_pts, s)) != SAL_OK)
+                return st;
+            if (!m->n_new && hipMalloc((void **)&m->n_new, sizeof(unsigned long long)) != hipSuccess)
+                return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(node counter)");
+        }
         const int64_t base_block = m->n[l + 1] / 8;
         LevelPtrs L2 = ptrs(m);
         SAL_HIP(hipEventRecord(m->ev[5], s));
         SAL_HIP(launch_split(L2, m->g, m->T, l, m->list + off[l], count[l], base_block,
                              nodes ? nullptr : m->cen[0], nodes ? nullptr : m->cen[1],
                              nodes ? nullptr : m->cen[2], s));
-        if (nodes)
-            SAL_HIP(launch_midpoints(L2, m->g, l, m->list + off[l], count[l], m->cen[0], m->cen[1],
-                                     m->cen[2], s));
+        if (nodes) {
+            // midpoints -> node table -> only the nodes not labeled before
+            SAL_HIP(launch_midpoints(L2, m->g, l, m->list + off[l], count[l], m->mid_xyz[0],
+                                     m->mid_xyz[1], m->mid_xyz[2], m->mid_key, s));
+            SAL_HIP(launch_fill_u64(m->n_new, 0ull, 1, s));
+            SAL_HIP(launch_node_insert(m->mid_key, n_pts, m->tkeys, m->tcap, m->mid_slot,
+                                       m->new_list, m->n_new, s));
+            SAL_HIP(launch_node_gather(m->new_list, m->n_new, n_pts, m->mid_xyz[0], m->mid_xyz[1],
+                                       m->mid_xyz[2], m->cen[0], m->cen[1], m->cen[2], s));
+            m->tused += n_pts;
+        }
         SAL_HIP(hipEventRecord(m->ev[6], s));
         m->n[l + 1] += kids;
         if (nodes) {
-            if ((st = label_scratch(ctx, m, set, n_pts, opt, m->lab_scratch, m->ev[10], m->ev[9],
-                                    m->mid_masks)) != SAL_OK)
+            if ((st = label_scratch_dev(ctx, m, set, n_pts, m->n_new, opt, m->lab_scratch,
+                                        m->ev[10], m->ev[9], m->new_masks)) != SAL_OK)
                 return st;
+            SAL_HIP(launch_node_store(m->new_list, m->n_new, n_pts, m->mid_slot, m->new_masks,
+                                      m->tmasks, s));
+            SAL_HIP(launch_node_fetch(m->mid_slot, n_pts, m->tmasks, m->mid_masks, s));
             SAL_HIP(launch_child_masks(L2, m->g, l, m->list + off[l], count[l], base_block,
                                        m->node0, m->vmask[l], m->mid_masks, m->vmask[l + 1],
                                        set->surf, s));
@@ -248,7 +330,13 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
         ms_recheck += elapsed(m->ev[9], m->ev[7]);
         if (l + 1 > m->max_level) m->max_level = l + 1;
         n_split += count[l];
-        n_label += n_pts;
+        if (nodes) {
+            unsigned long long fresh = 0;
+            SAL_HIP(hipMemcpy(&fresh, m->n_new, sizeof(fresh), hipMemcpyDeviceToHost));
+            n_label += (int64_t)fresh;
+        } else {
+            n_label += n_pts;
+        }
     }
     m->n_leaves += 7 * n_split;
     SAL_HIP(hipEventRecord(m->ev[8], s));
@@ -503,6 +591,12 @@ void sal_tet_mesh_destroy(sal_tet_mesh *m) {
     for (auto *v : m->vmask)
         if (v) (void)hipFree(v);
     if (m->mid_masks) (void)hipFree(m->mid_masks);
+    for (auto *p : m->mid_xyz)
+        if (p) (void)hipFree(p);
+    void *more[] = {m->mid_key, m->mid_slot, m->new_list, m->new_masks, m->n_new, m->tkeys,
+                    m->tmasks};
+    for (void *p : more)
+        if (p) (void)hipFree(p);
     if (m->rs) (void)hipFree(m->rs);
     if (m->round_graph) (void)hipGraphExecDestroy(m->round_graph);
     for (auto &e : m->ev)

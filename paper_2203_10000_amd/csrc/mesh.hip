@@ -372,7 +372,7 @@ __global__ void k_elem_from_nodes0(LatticeGeom g, int64_t n0,
 // (X_a + X_b), products and sums rounded once in double, then to float.
 __global__ void k_midpoints(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
                             int64_t count, float *__restrict__ mx, float *__restrict__ my,
-                            float *__restrict__ mz) {
+                            float *__restrict__ mz, uint64_t *__restrict__ mkey) {
     const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (jj >= count * 6) return;
     const int64_t j = jj / 6;
@@ -387,6 +387,107 @@ __global__ void k_midpoints(LevelPtrs L, LatticeGeom g, int l, const int32_t *__
     float *out[3] = {mx, my, mz};
     for (int a = 0; a < 3; ++a)
         out[a][jj] = (float)__dadd_rn(g.origin[a], __dmul_rn(hl, (double)(X[ea[e]][a] + X[eb[e]][a])));
+    // node key: coordinates on the level-kMaxLevels grid, 21 bits each
+    const int sh = kMaxLevels - (l + 1);
+    uint64_t key = 0;
+    for (int a = 0; a < 3; ++a)
+        key = (key << 21) | (uint64_t)((X[ea[e]][a] + X[eb[e]][a]) << sh);
+    mkey[jj] = key;
+}
+
+// ------------------------------------------------------------ node table
+// Open-addressing hash table of the nodes labeled after a split (keys on the
+// finest grid, linear probing), so a node shared by several split leaves, or
+// labeled in an earlier round, is labeled once.
+constexpr uint64_t kEmptyKey = ~0ull;
+
+__device__ __forceinline__ uint64_t node_hash(uint64_t k) {
+    // splitmix64 finaliser
+    k ^= k >> 30;
+    k *= 0xbf58476d1ce4e5b9ull;
+    k ^= k >> 27;
+    k *= 0x94d049bb133111ebull;
+    k ^= k >> 31;
+    return k;
+}
+
+// Inserts every midpoint key; the thread whose insert creates the entry lists
+// the midpoint as a new node.  slot[jj] = the key's table slot.
+__global__ void k_node_insert(const uint64_t *__restrict__ mkey, int64_t n,
+                              unsigned long long *__restrict__ tkeys, int64_t cap,
+                              int64_t *__restrict__ slot, int32_t *__restrict__ new_list,
+                              unsigned long long *__restrict__ n_new) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= n) return;
+    const uint64_t key = mkey[jj];
+    uint64_t h = node_hash(key) & (uint64_t)(cap - 1);
+    for (int64_t probe = 0; probe < cap; ++probe) {
+        const unsigned long long prev = atomicCAS(&tkeys[h], kEmptyKey, key);
+        if (prev == kEmptyKey) {
+            slot[jj] = (int64_t)h;
+            new_list[atomicAdd(n_new, 1ull)] = (int32_t)jj;
+            return;
+        }
+        if (prev == key) {
+            slot[jj] = (int64_t)h;
+            return;
+        }
+        h = (h + 1) & (uint64_t)(cap - 1);
+    }
+    slot[jj] = -1;   // table full (the host keeps it at most half full)
+}
+
+// The new nodes' coordinates, compacted for labeling.
+__global__ void k_node_gather(const int32_t *__restrict__ new_list,
+                              const unsigned long long *__restrict__ n_new,
+                              const float *__restrict__ mx, const float *__restrict__ my,
+                              const float *__restrict__ mz, float *__restrict__ x,
+                              float *__restrict__ y, float *__restrict__ z) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)*n_new) return;
+    const int32_t jj = new_list[t];
+    x[t] = mx[jj];
+    y[t] = my[jj];
+    z[t] = mz[jj];
+}
+
+__global__ void k_node_store(const int32_t *__restrict__ new_list,
+                             const unsigned long long *__restrict__ n_new,
+                             const int64_t *__restrict__ slot,
+                             const unsigned long long *__restrict__ masks,
+                             unsigned long long *__restrict__ tmasks) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)*n_new) return;
+    tmasks[slot[new_list[t]]] = masks[t];
+}
+
+// Midpoint masks from the table, in midpoint order.
+__global__ void k_node_fetch(const int64_t *__restrict__ slot, int64_t n,
+                             const unsigned long long *__restrict__ tmasks,
+                             unsigned long long *__restrict__ out) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= n) return;
+    const int64_t sl = slot[jj];
+    out[jj] = sl >= 0 ? tmasks[sl] : 0ull;
+}
+
+// Re-inserts the entries of an old table into a larger one.
+__global__ void k_node_rehash(const unsigned long long *__restrict__ okeys,
+                              const unsigned long long *__restrict__ omasks, int64_t ocap,
+                              unsigned long long *__restrict__ tkeys,
+                              unsigned long long *__restrict__ tmasks, int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ocap) return;
+    const uint64_t key = okeys[i];
+    if (key == kEmptyKey) return;
+    uint64_t h = node_hash(key) & (uint64_t)(cap - 1);
+    for (int64_t probe = 0; probe < cap; ++probe) {
+        if (atomicCAS(&tkeys[h], kEmptyKey, key) == kEmptyKey) {
+            tmasks[h] = omasks[i];
+            return;
+        }
+        h = (h + 1) & (uint64_t)(cap - 1);
+    }
 }
 
 // Vertex masks and labels of the 8 children of every listed level-l leaf:
@@ -573,9 +674,49 @@ hipError_t launch_elem_from_nodes0(const LatticeGeom &g, int64_t n0,
 }
 
 hipError_t launch_midpoints(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
-                            int64_t count, float *mx, float *my, float *mz, hipStream_t s) {
+                            int64_t count, float *mx, float *my, float *mz, uint64_t *mkey,
+                            hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    k_midpoints<<<grid_for(count * 6, 256), 256, 0, s>>>(L, g, l, list, count, mx, my, mz);
+    k_midpoints<<<grid_for(count * 6, 256), 256, 0, s>>>(L, g, l, list, count, mx, my, mz, mkey);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_insert(const uint64_t *mkey, int64_t n, unsigned long long *tkeys,
+                              int64_t cap, int64_t *slot, int32_t *new_list,
+                              unsigned long long *n_new, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_node_insert<<<grid_for(n, 256), 256, 0, s>>>(mkey, n, tkeys, cap, slot, new_list, n_new);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_gather(const int32_t *new_list, const unsigned long long *n_new,
+                              int64_t n_cap, const float *mx, const float *my, const float *mz,
+                              float *x, float *y, float *z, hipStream_t s) {
+    if (n_cap <= 0) return hipSuccess;
+    k_node_gather<<<grid_for(n_cap, 256), 256, 0, s>>>(new_list, n_new, mx, my, mz, x, y, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_store(const int32_t *new_list, const unsigned long long *n_new,
+                             int64_t n_cap, const int64_t *slot, const unsigned long long *masks,
+                             unsigned long long *tmasks, hipStream_t s) {
+    if (n_cap <= 0) return hipSuccess;
+    k_node_store<<<grid_for(n_cap, 256), 256, 0, s>>>(new_list, n_new, slot, masks, tmasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_fetch(const int64_t *slot, int64_t n, const unsigned long long *tmasks,
+                             unsigned long long *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_node_fetch<<<grid_for(n, 256), 256, 0, s>>>(slot, n, tmasks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_rehash(const unsigned long long *okeys, const unsigned long long *omasks,
+                              int64_t ocap, unsigned long long *tkeys, unsigned long long *tmasks,
+                              int64_t cap, hipStream_t s) {
+    if (ocap <= 0) return hipSuccess;
+    k_node_rehash<<<grid_for(ocap, 256), 256, 0, s>>>(okeys, omasks, ocap, tkeys, tmasks, cap);
     return hipGetLastError();
 }
 

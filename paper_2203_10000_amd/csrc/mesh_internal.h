@@ -96,7 +96,24 @@ hipError_t launch_elem_from_nodes0(const LatticeGeom &g, int64_t n0,
                                    const unsigned long long *node0, const SurfaceDev *surf,
                                    int32_t *label0, hipStream_t s);
 hipError_t launch_midpoints(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
-                            int64_t count, float *mx, float *my, float *mz, hipStream_t s);
+                            int64_t count, float *mx, float *my, float *mz, uint64_t *mkey,
+                            hipStream_t s);
+// Node table (open addressing; keys ~0 = empty; the host keeps it at most
+// half full).
+hipError_t launch_node_insert(const uint64_t *mkey, int64_t n, unsigned long long *tkeys,
+                              int64_t cap, int64_t *slot, int32_t *new_list,
+                              unsigned long long *n_new, hipStream_t s);
+hipError_t launch_node_gather(const int32_t *new_list, const unsigned long long *n_new,
+                              int64_t n_cap, const float *mx, const float *my, const float *mz,
+                              float *x, float *y, float *z, hipStream_t s);
+hipError_t launch_node_store(const int32_t *new_list, const unsigned long long *n_new,
+                             int64_t n_cap, const int64_t *slot, const unsigned long long *masks,
+                             unsigned long long *tmasks, hipStream_t s);
+hipError_t launch_node_fetch(const int64_t *slot, int64_t n, const unsigned long long *tmasks,
+                             unsigned long long *out, hipStream_t s);
+hipError_t launch_node_rehash(const unsigned long long *okeys, const unsigned long long *omasks,
+                              int64_t ocap, unsigned long long *tkeys, unsigned long long *tmasks,
+                              int64_t cap, hipStream_t s);
 hipError_t launch_child_masks(const LevelPtrs &L, const LatticeGeom &g, int l,
                               const int32_t *list, int64_t count, int64_t base_block,
                               const unsigned long long *node0,

@@ -167,7 +167,7 @@ def test_four_node_rule_two_rounds(ctx, node_oracle, precision):
     for r in (1, 2):
         assert st[r]["n_boundary"] == ost[r]["boundary"]
         assert st[r]["n_leaves"] == ost[r]["leaves"]
-        assert st[r]["n_labeled"] == 6 * ost[r]["boundary"]   # six midpoints per split
+        assert st[r]["n_labeled"] == ost[r]["nodes"]   # each new node labeled once
 
 
 def test_four_node_rule_asked_for_a_graph_runs_host_driven(ctx, node_oracle):
