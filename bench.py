@@ -53,14 +53,24 @@ def parse():
 
 def calibrate_copy():
     """A plain device-to-device copy of 1 GiB, three times: reads and writes
-    exactly 1 GiB each per launch, the reference for FETCH_SIZE / WRITE_SIZE."""
+    exactly 1 GiB each per launch, the reference for FETCH_SIZE / WRITE_SIZE.
+    Also reports the copy's achieved HBM rate (read + write bytes per second)
+    as a check of the bandwidth side of the roofline."""
     import torch
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(3):
         dst.copy_(src)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
+    ms = e0.elapsed_time(e1) / 3
+    nbytes = src.numel() * 4
+    print(json.dumps({"copy_bytes": nbytes, "launches": 4, "ms_per_copy": ms,
+                      "hbm_gb_per_s": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def source_digest():
