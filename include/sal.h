@@ -275,6 +275,44 @@ sal_status sal_tet_mesh_size(const sal_tet_mesh *mesh, int64_t *n_leaves, int32_
 sal_status sal_tet_mesh_export(sal_context *ctx, const sal_tet_mesh *mesh, uint64_t *keys,
                                int32_t *labels, float *cx, float *cy, float *cz);
 
+/* ---------------------------------------------- conforming transition mesh */
+typedef struct sal_conform_info {
+    int64_t n_tets;           /* tetrahedra of the conforming mesh */
+    int64_t n_nodes;          /* distinct nodes */
+    int64_t n_leaves;         /* leaves after the closure */
+    int64_t n_by_pieces[4];   /* leaves cut into 1, 2, 3 and 4 tetrahedra */
+    int32_t closure_rounds;   /* rounds of 1 -> 8 closure splits */
+    int32_t reserved;
+} sal_conform_info;
+
+/* Section 2.1.2 (Fig. 2c-e): removes the hanging nodes that refinement left
+ * between leaves of different levels.  An edge of a leaf is hanging when its
+ * midpoint is a vertex of another leaf.  A leaf whose hanging edges are one
+ * edge, two edges of one face or the three edges of one face is cut into 2, 3
+ * or 4 tetrahedra (the quadrilateral of the two-edge case along its diagonal
+ * through the smallest node key, so that both sides of the face agree).  A
+ * leaf with any other pattern, or with a node at a quarter point of an edge
+ * (a neighbour two levels finer), is split 1 -> 8, its children keeping its
+ * label, and the patterns are found again until none is left (closure).  The
+ * result is stored on the mesh: tetrahedra over numbered nodes, each with the
+ * label of the leaf it comes from.  Nodes are the points of the level-3 grid
+ * (spacing h / 8), numbered in ascending key order, key = (i << 42) |
+ * (j << 21) | k with (i, j, k) the level-3 grid coordinates.  Tetrahedra are
+ * positively oriented; their order is that of their leaves as
+ * sal_tet_mesh_export lists them.  After this call the mesh cannot be refined
+ * again (SAL_ERR_INVALID_ARG), nor made conforming twice.
+ *   info  NULL, or filled after synchronising
+ * Errors: SAL_ERR_CAPACITY above 2^31 tetrahedron corners; SAL_ERR_OUT_OF_MEMORY. */
+sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *mesh, sal_conform_info *info);
+
+/* Copies the conforming mesh into caller device buffers (each may be NULL):
+ *   tets [n_tets][4] int32 node ids, labels [n_tets] int32,
+ *   xyz [n_nodes][3] float32 node coordinates (origin + key coordinate x h/8,
+ *   rounded once from double), node_keys [n_nodes] int64.
+ * Errors: SAL_ERR_INVALID_ARG before sal_tet_mesh_conform. */
+sal_status sal_tet_mesh_export_conforming(sal_context *ctx, const sal_tet_mesh *mesh, int32_t *tets,
+                                          int32_t *labels, float *xyz, int64_t *node_keys);
+
 /* ------------------------------------------------------------ batched form
  * Many independent labeling problems in one persistent launch: the work is
  * cut into (instance, point block, surface, triangle range) items ordered by

@@ -77,6 +77,17 @@ class RefineStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ConformInfo(ctypes.Structure):
+    _fields_ = [("n_tets", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("n_by_pieces", ctypes.c_int64 * 4),
+                ("closure_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["n_by_pieces"] = list(self.n_by_pieces)
+        return d
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("surfaces", ctypes.c_void_p), ("n_points", ctypes.c_int64),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
@@ -111,6 +122,8 @@ _SIGNATURES = [
     ("sal_tet_mesh_size", ctypes.c_int,
      [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     ("sal_tet_mesh_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("sal_tet_mesh_conform", ctypes.c_int, [_P, _P, ctypes.POINTER(ConformInfo)]),
+    ("sal_tet_mesh_export_conforming", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("sal_label_batch", ctypes.c_int,
      [_P, ctypes.POINTER(Instance), ctypes.c_int32, ctypes.POINTER(LabelOptions),
       ctypes.POINTER(LabelStats)]),
@@ -272,7 +285,8 @@ def label_points(ctx, sset, points, precision="fp32", winding=None, stats=False,
 
 
 class TetMesh:
-    """sal_tet_mesh_create_lattice / sal_refine_relabel / sal_tet_mesh_export."""
+    """sal_tet_mesh_create_lattice / sal_refine_relabel / sal_tet_mesh_export /
+    sal_tet_mesh_conform / sal_tet_mesh_export_conforming."""
 
     def __init__(self, ctx, origin, h, cells):
         self.ctx = ctx
@@ -308,6 +322,28 @@ class TetMesh:
             self.ctx.handle, self.handle, _ptr(out["keys"]), _ptr(out["labels"]),
             _ptr(cen[0] if cen is not None else None), _ptr(cen[1] if cen is not None else None),
             _ptr(cen[2] if cen is not None else None)))
+        return out
+
+    def conform(self):
+        """sal_tet_mesh_conform: the conforming transition mesh; returns its info."""
+        info = ConformInfo()
+        _check(lib().sal_tet_mesh_conform(self.ctx.handle, self.handle, ctypes.byref(info)))
+        self.conform_info = info.as_dict()
+        return self.conform_info
+
+    def export_conforming(self):
+        """sal_tet_mesh_export_conforming: {"tets" [m, 4] int32 node ids,
+        "labels" [m], "xyz" [n, 3] float32, "node_keys" [n] int64}."""
+        import torch
+        info = self.conform_info
+        dev = torch.device("cuda", self.ctx.device)
+        out = {"tets": torch.empty((info["n_tets"], 4), dtype=torch.int32, device=dev),
+               "labels": torch.empty(info["n_tets"], dtype=torch.int32, device=dev),
+               "xyz": torch.empty((info["n_nodes"], 3), dtype=torch.float32, device=dev),
+               "node_keys": torch.empty(info["n_nodes"], dtype=torch.int64, device=dev)}
+        _check(lib().sal_tet_mesh_export_conforming(
+            self.ctx.handle, self.handle, _ptr(out["tets"]), _ptr(out["labels"]),
+            _ptr(out["xyz"]), _ptr(out["node_keys"])))
         return out
 
     def close(self):

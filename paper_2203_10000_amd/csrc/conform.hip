@@ -1,0 +1,332 @@
+// Conforming transition refinement of the leaf set (paper section 2.1.2,
+// Fig. 2c-e) and the conforming mesh it gives: explicit tetrahedra over
+// numbered nodes.
+//
+// A leaf edge is *hanging* when its midpoint is a vertex of another leaf; a
+// node at a quarter point means a neighbour two or more levels finer.  The
+// patterns the paper splits are one hanging edge (2 tetrahedra), two hanging
+// edges of one face (3) and the three edges of one face (4); a leaf with any
+// other pattern is split into its 8 children (labels kept) and the patterns
+// are found again (closure, driven from mesh.cpp).  Nodes are points of the
+// finest grid (level kMaxLevels), keyed by 21-bit coordinates.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "kuhn_dev.h"
+#include "mesh_internal.h"
+
+namespace sal {
+namespace {
+
+constexpr uint64_t kEmpty = ~0ull;
+
+// The four vertices of leaf (l, i) on the finest grid.
+__device__ __forceinline__ void leaf_fine_vertices(const LevelPtrs &L, const LatticeGeom &g, int l,
+                                                   int64_t i, int64_t F[4][3]) {
+    int lk, q;
+    int64_t c[3];
+    split_key(entry_key(L, g, l, i), lk, q, c);
+    kuhn_vertices(q, c, F);
+    const int sh = kMaxLevels - l;
+    for (int v = 0; v < 4; ++v)
+        for (int a = 0; a < 3; ++a) F[v][a] <<= sh;
+}
+
+__device__ __forceinline__ uint64_t fine_key(const int64_t f[3]) {
+    return ((uint64_t)f[0] << 42) | ((uint64_t)f[1] << 21) | (uint64_t)f[2];
+}
+
+__device__ __forceinline__ uint64_t set_hash(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ bool set_find(const unsigned long long *tkeys, int64_t cap, uint64_t key) {
+    uint64_t h = set_hash(key) & (uint64_t)(cap - 1);
+    for (int64_t probe = 0; probe < cap; ++probe) {
+        const uint64_t k = tkeys[h];
+        if (k == key) return true;
+        if (k == kEmpty) return false;
+        h = (h + 1) & (uint64_t)(cap - 1);
+    }
+    return false;
+}
+
+__global__ void k_insert_vertices(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
+                                  int64_t count, unsigned long long *__restrict__ tkeys, int64_t cap,
+                                  unsigned long long *__restrict__ overflow) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= 4 * count) return;
+    int64_t F[4][3];
+    leaf_fine_vertices(L, g, l, list[jj >> 2], F);
+    const uint64_t key = fine_key(F[jj & 3]);
+    uint64_t h = set_hash(key) & (uint64_t)(cap - 1);
+    for (int64_t probe = 0; probe < cap; ++probe) {
+        const unsigned long long prev = atomicCAS(&tkeys[h], kEmpty, key);
+        if (prev == kEmpty || prev == key) return;
+        h = (h + 1) & (uint64_t)(cap - 1);
+    }
+    atomicAdd(overflow, 1ull);
+}
+
+constexpr int kEdgeA[6] = {0, 0, 0, 1, 1, 2};
+constexpr int kEdgeB[6] = {1, 2, 3, 2, 3, 3};
+
+__device__ __forceinline__ bool allowed_pattern(unsigned bits) {
+    const int n = __popc(bits);
+    if (n <= 1) return true;
+    if (n > 3) return false;
+    unsigned verts = 0;
+    for (int e = 0; e < 6; ++e)
+        if (bits >> e & 1u) verts |= (1u << kEdgeA[e]) | (1u << kEdgeB[e]);
+    return __popc(verts) == 3;   // two edges sharing a vertex, or the edges of one face
+}
+
+// Hanging-edge bits of every listed leaf (in list order) and the red flag of
+// the leaves whose pattern the paper does not split.
+__global__ void k_leaf_pattern(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
+                               int64_t count, const unsigned long long *__restrict__ tkeys,
+                               int64_t cap, uint8_t *__restrict__ bits_out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const int64_t i = list[j];
+    int64_t F[4][3];
+    leaf_fine_vertices(L, g, l, i, F);
+    unsigned bits = 0;
+    bool deep = false;
+    for (int e = 0; e < 6; ++e) {
+        const int a = kEdgeA[e], b = kEdgeB[e];
+        if (l < kMaxLevels) {
+            int64_t m[3];
+            for (int x = 0; x < 3; ++x) m[x] = (F[a][x] + F[b][x]) >> 1;
+            if (set_find(tkeys, cap, fine_key(m))) bits |= 1u << e;
+        }
+        if (l + 2 <= kMaxLevels) {
+            int64_t q1[3], q2[3];
+            for (int x = 0; x < 3; ++x) {
+                q1[x] = (3 * F[a][x] + F[b][x]) >> 2;
+                q2[x] = (F[a][x] + 3 * F[b][x]) >> 2;
+            }
+            deep |= set_find(tkeys, cap, fine_key(q1)) || set_find(tkeys, cap, fine_key(q2));
+        }
+    }
+    bits_out[j] = (uint8_t)bits;
+    L.flag[l][i] = (deep || !allowed_pattern(bits)) ? 1 : 0;
+}
+
+__global__ void k_tet_counts(const uint8_t *__restrict__ bits, int64_t count,
+                             int32_t *__restrict__ counts) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    counts[j] = 1 + __popc((unsigned)bits[j]);
+}
+
+__device__ __forceinline__ void put_tet(int64_t *__restrict__ out, int64_t slot, const int64_t a[3],
+                                        const int64_t b[3], const int64_t c[3], const int64_t d[3]) {
+    // positive orientation: det(b - a, c - a, d - a) > 0, else swap a and b
+    const int64_t u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const int64_t v[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const int64_t w[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
+    const int64_t det = u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) +
+                        u[2] * (v[0] * w[1] - v[1] * w[0]);
+    int64_t *o = out + 4 * slot;
+    o[0] = (int64_t)fine_key(det > 0 ? a : b);
+    o[1] = (int64_t)fine_key(det > 0 ? b : a);
+    o[2] = (int64_t)fine_key(c);
+    o[3] = (int64_t)fine_key(d);
+}
+
+// The tetrahedra of every listed leaf at offsets[j] (first output slot).
+__global__ void k_emit(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
+                       int64_t count, const uint8_t *__restrict__ bits,
+                       const int64_t *__restrict__ offsets, int64_t *__restrict__ tets,
+                       int32_t *__restrict__ labels) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const int64_t i = list[j];
+    int64_t F[4][3];
+    leaf_fine_vertices(L, g, l, i, F);
+    const unsigned b = bits[j];
+    const int n = __popc(b);
+    const int64_t o = offsets[j];
+    const int32_t lab = L.label[l][i];
+    for (int t = 0; t <= n; ++t) labels[o + t] = lab;
+    if (n == 0) {
+        put_tet(tets, o, F[0], F[1], F[2], F[3]);
+        return;
+    }
+    int ed[3], k = 0;
+    for (int e = 0; e < 6; ++e)
+        if (b >> e & 1u) ed[k++] = e;
+    if (n == 1) {
+        const int x = kEdgeA[ed[0]], y = kEdgeB[ed[0]];
+        int r[2], m = 0;
+        for (int v = 0; v < 4; ++v)
+            if (v != x && v != y) r[m++] = v;
+        int64_t mid[3];
+        for (int a = 0; a < 3; ++a) mid[a] = (F[x][a] + F[y][a]) >> 1;
+        put_tet(tets, o, F[x], mid, F[r[0]], F[r[1]]);
+        put_tet(tets, o + 1, mid, F[y], F[r[0]], F[r[1]]);
+        return;
+    }
+    if (n == 2) {
+        const int e0a = kEdgeA[ed[0]], e0b = kEdgeB[ed[0]];
+        const int e1a = kEdgeA[ed[1]], e1b = kEdgeB[ed[1]];
+        const int a = (e0a == e1a || e0a == e1b) ? e0a : e0b;   // the shared vertex
+        const int bv = e0a + e0b - a, cv = e1a + e1b - a;
+        const int d = 6 - a - bv - cv;
+        int64_t m1[3], m2[3];
+        for (int x = 0; x < 3; ++x) {
+            m1[x] = (F[a][x] + F[bv][x]) >> 1;
+            m2[x] = (F[a][x] + F[cv][x]) >> 1;
+        }
+        put_tet(tets, o, F[a], m1, m2, F[d]);
+        // the quadrilateral (m1, b, c, m2) is cut along the diagonal through
+        // its smallest node key, a property of the face alone
+        const uint64_t km1 = fine_key(m1), kb = fine_key(F[bv]), kc = fine_key(F[cv]),
+                       km2 = fine_key(m2);
+        const uint64_t low = min(min(km1, kb), min(kc, km2));
+        if (low == km1 || low == kc) {
+            put_tet(tets, o + 1, m1, F[bv], F[cv], F[d]);
+            put_tet(tets, o + 2, m1, F[cv], m2, F[d]);
+        } else {
+            put_tet(tets, o + 1, m1, F[bv], m2, F[d]);
+            put_tet(tets, o + 2, F[bv], F[cv], m2, F[d]);
+        }
+        return;
+    }
+    // three edges of one face (a < b < c), apex d
+    unsigned vm = 0;
+    for (int q = 0; q < 3; ++q) vm |= (1u << kEdgeA[ed[q]]) | (1u << kEdgeB[ed[q]]);
+    int fv[3], m = 0, d = 0;
+    for (int v = 0; v < 4; ++v) {
+        if (vm >> v & 1u) fv[m++] = v;
+        else d = v;
+    }
+    int64_t mab[3], mbc[3], mca[3];
+    for (int x = 0; x < 3; ++x) {
+        mab[x] = (F[fv[0]][x] + F[fv[1]][x]) >> 1;
+        mbc[x] = (F[fv[1]][x] + F[fv[2]][x]) >> 1;
+        mca[x] = (F[fv[2]][x] + F[fv[0]][x]) >> 1;
+    }
+    put_tet(tets, o, F[fv[0]], mab, mca, F[d]);
+    put_tet(tets, o + 1, mab, F[fv[1]], mbc, F[d]);
+    put_tet(tets, o + 2, mca, mbc, F[fv[2]], F[d]);
+    put_tet(tets, o + 3, mab, mbc, mca, F[d]);
+}
+
+__global__ void k_head_flags(const int64_t *__restrict__ sorted, int64_t n, int32_t *__restrict__ head) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    head[i] = (i == 0 || sorted[i] != sorted[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_unique_scatter(const int64_t *__restrict__ sorted, const int32_t *__restrict__ head,
+                                 const int64_t *__restrict__ pos, int64_t n,
+                                 int64_t *__restrict__ nodes) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (head[i]) nodes[pos[i]] = sorted[i];
+}
+
+__global__ void k_node_ids(const int64_t *__restrict__ tet_keys, int64_t n,
+                           const int64_t *__restrict__ nodes, int64_t n_nodes,
+                           int32_t *__restrict__ ids) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t key = tet_keys[i];
+    int64_t lo = 0, hi = n_nodes - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (nodes[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    ids[i] = (int32_t)lo;
+}
+
+__global__ void k_node_xyz(LatticeGeom g, const int64_t *__restrict__ nodes, int64_t n,
+                           float *__restrict__ xyz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = (uint64_t)nodes[i];
+    const int64_t f[3] = {(int64_t)((k >> 42) & 0x1fffffu), (int64_t)((k >> 21) & 0x1fffffu),
+                          (int64_t)(k & 0x1fffffu)};
+    const double hf = ldexp(g.h, -kMaxLevels);
+    for (int a = 0; a < 3; ++a)
+        xyz[3 * i + a] = lattice_coord(g.origin[a], hf, (double)f[a]);
+}
+
+inline unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_insert_vertices(const LevelPtrs &L, const LatticeGeom &g, int l,
+                                  const int32_t *list, int64_t count, unsigned long long *tkeys,
+                                  int64_t cap, unsigned long long *overflow, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_insert_vertices<<<grid_of(4 * count), 256, 0, s>>>(L, g, l, list, count, tkeys, cap, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_pattern(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
+                               int64_t count, const unsigned long long *tkeys, int64_t cap,
+                               uint8_t *bits, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_leaf_pattern<<<grid_of(count), 256, 0, s>>>(L, g, l, list, count, tkeys, cap, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_tet_counts(const uint8_t *bits, int64_t count, int32_t *counts, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_tet_counts<<<grid_of(count), 256, 0, s>>>(bits, count, counts);
+    return hipGetLastError();
+}
+
+hipError_t exclusive_sum_i32(const int32_t *in, int64_t *out, int64_t n, void *tmp,
+                             size_t *tmp_bytes, hipStream_t s) {
+    return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, s);
+}
+
+hipError_t launch_emit(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
+                       int64_t count, const uint8_t *bits, const int64_t *offsets, int64_t *tets,
+                       int32_t *labels, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_emit<<<grid_of(count), 256, 0, s>>>(L, g, l, list, count, bits, offsets, tets, labels);
+    return hipGetLastError();
+}
+
+hipError_t sort_keys_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
+                         hipStream_t s) {
+    return hipcub::DeviceRadixSort::SortKeys(tmp, *tmp_bytes, in, out, (int)n, 0, 64, s);
+}
+
+hipError_t launch_unique(const int64_t *sorted, int64_t n, int32_t *head, int64_t *pos,
+                         int64_t *nodes, void *tmp, size_t *tmp_bytes, hipStream_t s) {
+    if (!tmp) return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, head, pos, (int)n, s);
+    if (n <= 0) return hipSuccess;
+    k_head_flags<<<grid_of(n), 256, 0, s>>>(sorted, n, head);
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, head, pos, (int)n, s);
+    if (e != hipSuccess) return e;
+    k_unique_scatter<<<grid_of(n), 256, 0, s>>>(sorted, head, pos, n, nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_ids(const int64_t *tet_keys, int64_t n, const int64_t *nodes, int64_t n_nodes,
+                           int32_t *ids, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_node_ids<<<grid_of(n), 256, 0, s>>>(tet_keys, n, nodes, n_nodes, ids);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_xyz(const LatticeGeom &g, const int64_t *nodes, int64_t n, float *xyz,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_node_xyz<<<grid_of(n), 256, 0, s>>>(g, nodes, n, xyz);
+    return hipGetLastError();
+}
+
+}  // namespace sal

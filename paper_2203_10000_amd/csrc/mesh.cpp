@@ -3,9 +3,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "mesh_internal.h"
 #include "runtime.h"
@@ -54,6 +56,13 @@ struct sal_tet_mesh {
     uint8_t *flag[sal::kMaxLevels + 1] = {};
     int max_level = 0;
     bool labeled0 = false;
+    // conforming mesh (sal_tet_mesh_conform); no refinement after it
+    bool conformed = false;
+    int64_t conf_tets = 0, conf_nodes = 0;
+    int32_t *conf_ids = nullptr;     // [conf_tets][4] node ids
+    int32_t *conf_labels = nullptr;  // [conf_tets]
+    int64_t *conf_keys = nullptr;    // [conf_nodes] node keys, ascending
+    float *conf_xyz = nullptr;       // [conf_nodes][3]
     int64_t n_leaves = 0;
     // scratch
     float *cen[3] = {};
@@ -569,6 +578,29 @@ sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set
 
 using namespace sal;
 
+namespace sal {
+namespace {
+
+// Device scratch freed when the call ends.
+struct DevScratch {
+    std::vector<void *> bufs;
+    ~DevScratch() {
+        for (void *p : bufs) (void)hipFree(p);
+    }
+    template <typename T>
+    sal_status get(T **p, int64_t n) {
+        void *q = nullptr;
+        const size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+        if (hipMalloc(&q, bytes) != hipSuccess) return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conform)");
+        bufs.push_back(q);
+        *p = (T *)q;
+        return SAL_OK;
+    }
+};
+
+}  // namespace
+}  // namespace sal
+
 extern "C" {
 
 void sal_tet_mesh_destroy(sal_tet_mesh *m) {
@@ -587,6 +619,9 @@ void sal_tet_mesh_destroy(sal_tet_mesh *m) {
     if (m->blocks) (void)hipFree(m->blocks);
     if (m->totals) (void)hipFree(m->totals);
     if (m->lab_scratch) (void)hipFree(m->lab_scratch);
+    void *conf[] = {m->conf_ids, m->conf_labels, m->conf_keys, m->conf_xyz};
+    for (void *p : conf)
+        if (p) (void)hipFree(p);
     if (m->node0) (void)hipFree(m->node0);
     for (auto *v : m->vmask)
         if (v) (void)hipFree(v);
@@ -666,6 +701,8 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
         sal_status st = resolve_options(opt_in, &opt);
         if (st != SAL_OK) return st;
         opt.winding_type = SAL_WINDING_NONE;
+        if (m->conformed)
+            return set_error(SAL_ERR_INVALID_ARG, "the mesh was made conforming; it cannot be refined");
         if (m->max_level + rounds > kMaxLevels)
             return set_error(SAL_ERR_CAPACITY, "at most 3 refinement levels");
         SAL_HIP(hipSetDevice(ctx->device));
@@ -738,6 +775,194 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
     } catch (...) {
         return set_error(SAL_ERR_INTERNAL, "exception in sal_refine_relabel");
     }
+}
+
+sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_info *info) {
+    try {
+        if (!ctx || !m) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+        if (m->device != ctx->device) return set_error(SAL_ERR_INVALID_ARG, "mesh lives on another device");
+        if (m->conformed) return set_error(SAL_ERR_INVALID_ARG, "the mesh is already conforming");
+        SAL_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = ctx->stream;
+        sal_status st;
+        DevScratch keep;                 // lives to the end of the call
+        uint8_t *bits = nullptr;         // hanging-edge bits of the listed leaves
+        int64_t count[kMaxLevels + 1], off[kMaxLevels + 2], n_all = 0;
+        int rounds = 0;
+        for (;;) {
+            DevScratch iter;             // freed at the end of each closure round
+            // the leaves of every level, in index order
+            std::memset(count, 0, sizeof(count));
+            std::memset(off, 0, sizeof(off));
+            for (int l = 0; l <= m->max_level; ++l) off[l + 1] = off[l] + m->n[l];
+            if ((st = ensure_buf(&m->list, &m->list_cap, off[m->max_level + 1], s)) != SAL_OK) return st;
+            for (int l = 0; l <= m->max_level; ++l) {
+                CompactSrc src{nullptr, m->child[l]};
+                if ((st = compact(m, src, m->n[l], m->list + off[l], m->totals + l, s)) != SAL_OK)
+                    return st;
+            }
+            SAL_HIP(hipMemcpyAsync(count, m->totals, sizeof(int64_t) * (m->max_level + 1),
+                                   hipMemcpyDeviceToHost, s));
+            SAL_HIP(hipStreamSynchronize(s));
+            n_all = 0;
+            for (int l = 0; l <= m->max_level; ++l) n_all += count[l];
+            if (n_all != m->n_leaves) return set_error(SAL_ERR_INTERNAL, "leaf count mismatch");
+            // the set of all leaf vertices (finest-grid keys); grown on overflow
+            int64_t cap = 1 << 16;
+            while (cap < 2 * n_all) cap <<= 1;
+            unsigned long long *set = nullptr, *overflow = nullptr;
+            if ((st = iter.get(&overflow, 1)) != SAL_OK) return st;
+            LevelPtrs L = ptrs(m);
+            for (;;) {
+                if ((st = iter.get(&set, cap)) != SAL_OK) return st;
+                SAL_HIP(launch_fill_u64(set, ~0ull, cap, s));
+                SAL_HIP(launch_fill_u64(overflow, 0ull, 1, s));
+                for (int l = 0; l <= m->max_level; ++l)
+                    SAL_HIP(launch_insert_vertices(L, m->g, l, m->list + off[l], count[l], set, cap,
+                                                   overflow, s));
+                unsigned long long over = 0;
+                SAL_HIP(hipMemcpyAsync(&over, overflow, sizeof(over), hipMemcpyDeviceToHost, s));
+                SAL_HIP(hipStreamSynchronize(s));
+                if (!over) break;
+                cap <<= 2;
+            }
+            // hanging patterns, and red flags on the leaves the paper does not split
+            if ((st = keep.get(&bits, n_all)) != SAL_OK) return st;
+            for (int l = 0; l <= m->max_level; ++l) SAL_HIP(launch_fill_u8(m->flag[l], 0, m->n[l], s));
+            int64_t boff = 0;
+            for (int l = 0; l <= m->max_level; boff += count[l], ++l)
+                SAL_HIP(launch_leaf_pattern(L, m->g, l, m->list + off[l], count[l], set, cap,
+                                            bits + boff, s));
+            int32_t *red_list = nullptr;
+            if ((st = iter.get(&red_list, off[m->max_level + 1])) != SAL_OK) return st;
+            int64_t red[kMaxLevels + 1] = {0}, total_red = 0;
+            for (int l = 0; l <= m->max_level; ++l) {
+                CompactSrc src{m->flag[l], nullptr};
+                if ((st = compact(m, src, m->n[l], red_list + off[l], m->totals + l, s)) != SAL_OK)
+                    return st;
+            }
+            SAL_HIP(hipMemcpyAsync(red, m->totals, sizeof(int64_t) * (m->max_level + 1),
+                                   hipMemcpyDeviceToHost, s));
+            SAL_HIP(hipStreamSynchronize(s));
+            for (int l = 0; l <= m->max_level; ++l) total_red += red[l];
+            if (total_red == 0) break;
+            if (m->max_level == kMaxLevels && red[kMaxLevels] > 0)
+                return set_error(SAL_ERR_INTERNAL, "closure beyond level 3");
+            // red splits, deepest level first (its arrays never move under a
+            // pending split of a coarser level); children keep the label
+            for (int l = m->max_level; l >= 0; --l) {
+                if (red[l] == 0) continue;
+                const int64_t kids = 8 * red[l];
+                if ((st = ensure_level(m, l + 1, m->n[l + 1] + kids, s)) != SAL_OK) return st;
+                const int64_t base_block = m->n[l + 1] / 8;
+                LevelPtrs L2 = ptrs(m);
+                L2.inherit = 1;
+                SAL_HIP(launch_split(L2, m->g, m->T, l, red_list + off[l], red[l], base_block, nullptr,
+                                     nullptr, nullptr, s));
+                m->n[l + 1] += kids;
+                if (l + 1 > m->max_level) m->max_level = l + 1;
+                m->n_leaves += 7 * red[l];
+            }
+            SAL_HIP(hipStreamSynchronize(s));
+            ++rounds;
+        }
+
+        // the tetrahedra of each leaf, at the exclusive sum of the counts
+        int32_t *counts = nullptr;
+        int64_t *offsets = nullptr;
+        if ((st = keep.get(&counts, n_all)) != SAL_OK || (st = keep.get(&offsets, n_all)) != SAL_OK)
+            return st;
+        SAL_HIP(launch_tet_counts(bits, n_all, counts, s));
+        size_t tmp_bytes = 0;
+        SAL_HIP(exclusive_sum_i32(counts, offsets, n_all, nullptr, &tmp_bytes, s));
+        char *tmp = nullptr;
+        if ((st = keep.get(&tmp, (int64_t)tmp_bytes)) != SAL_OK) return st;
+        SAL_HIP(exclusive_sum_i32(counts, offsets, n_all, tmp, &tmp_bytes, s));
+        int64_t last_off = 0;
+        int32_t last_cnt = 0;
+        SAL_HIP(hipMemcpyAsync(&last_off, offsets + n_all - 1, sizeof(last_off), hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipMemcpyAsync(&last_cnt, counts + n_all - 1, sizeof(last_cnt), hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipStreamSynchronize(s));
+        const int64_t n_tets = last_off + last_cnt;
+        const int64_t n_corner = 4 * n_tets;
+        if (n_corner > INT32_MAX) return set_error(SAL_ERR_CAPACITY, "conforming mesh above 2^31 corners");
+        int64_t *tkeys = nullptr, *sorted = nullptr, *pos = nullptr, *nodes = nullptr;
+        int32_t *head = nullptr;
+        if ((st = keep.get(&tkeys, n_corner)) != SAL_OK || (st = keep.get(&sorted, n_corner)) != SAL_OK ||
+            (st = keep.get(&pos, n_corner)) != SAL_OK || (st = keep.get(&head, n_corner)) != SAL_OK ||
+            (st = keep.get(&nodes, n_corner)) != SAL_OK)
+            return st;
+        if (hipMalloc((void **)&m->conf_labels, (size_t)std::max<int64_t>(n_tets, 1) * sizeof(int32_t)) !=
+                hipSuccess ||
+            hipMalloc((void **)&m->conf_ids, (size_t)std::max<int64_t>(n_corner, 1) * sizeof(int32_t)) !=
+                hipSuccess)
+            return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conforming mesh)");
+        LevelPtrs L = ptrs(m);
+        int64_t boff = 0;
+        for (int l = 0; l <= m->max_level; boff += count[l], ++l)
+            SAL_HIP(launch_emit(L, m->g, l, m->list + off[l], count[l], bits + boff, offsets + boff,
+                                tkeys, m->conf_labels, s));
+        // nodes: the distinct corner keys in ascending order; ids by search
+        size_t sort_bytes = 0, uniq_bytes = 0;
+        SAL_HIP(sort_keys_i64(tkeys, sorted, n_corner, nullptr, &sort_bytes, s));
+        SAL_HIP(launch_unique(sorted, n_corner, head, pos, nodes, nullptr, &uniq_bytes, s));
+        tmp_bytes = std::max(sort_bytes, uniq_bytes);
+        if ((st = keep.get(&tmp, (int64_t)tmp_bytes)) != SAL_OK) return st;
+        SAL_HIP(sort_keys_i64(tkeys, sorted, n_corner, tmp, &tmp_bytes, s));
+        SAL_HIP(launch_unique(sorted, n_corner, head, pos, nodes, tmp, &tmp_bytes, s));
+        int64_t last_pos = 0;
+        int32_t last_head = 0;
+        SAL_HIP(hipMemcpyAsync(&last_pos, pos + n_corner - 1, sizeof(last_pos), hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipMemcpyAsync(&last_head, head + n_corner - 1, sizeof(last_head), hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipStreamSynchronize(s));
+        const int64_t n_nodes = last_pos + last_head;
+        if (hipMalloc((void **)&m->conf_keys, (size_t)std::max<int64_t>(n_nodes, 1) * sizeof(int64_t)) !=
+                hipSuccess ||
+            hipMalloc((void **)&m->conf_xyz, (size_t)std::max<int64_t>(3 * n_nodes, 1) * sizeof(float)) !=
+                hipSuccess)
+            return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conforming nodes)");
+        SAL_HIP(hipMemcpyAsync(m->conf_keys, nodes, (size_t)n_nodes * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+        SAL_HIP(launch_node_ids(tkeys, n_corner, m->conf_keys, n_nodes, m->conf_ids, s));
+        SAL_HIP(launch_node_xyz(m->g, m->conf_keys, n_nodes, m->conf_xyz, s));
+        std::vector<int32_t> hc((size_t)n_all);
+        SAL_HIP(hipMemcpyAsync(hc.data(), counts, (size_t)n_all * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipStreamSynchronize(s));
+        m->conf_tets = n_tets;
+        m->conf_nodes = n_nodes;
+        m->conformed = true;
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->n_tets = n_tets;
+            info->n_nodes = n_nodes;
+            info->n_leaves = n_all;
+            for (int32_t c : hc) info->n_by_pieces[std::min(std::max(c, 1), 4) - 1] += 1;
+            info->closure_rounds = rounds;
+        }
+        return SAL_OK;
+    } catch (...) {
+        return set_error(SAL_ERR_INTERNAL, "exception in sal_tet_mesh_conform");
+    }
+}
+
+sal_status sal_tet_mesh_export_conforming(sal_context *ctx, const sal_tet_mesh *m, int32_t *tets,
+                                          int32_t *labels, float *xyz, int64_t *node_keys) {
+    if (!ctx || !m) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+    if (!m->conformed) return set_error(SAL_ERR_INVALID_ARG, "call sal_tet_mesh_conform first");
+    SAL_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    if (tets)
+        SAL_HIP(hipMemcpyAsync(tets, m->conf_ids, (size_t)m->conf_tets * 4 * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, s));
+    if (labels)
+        SAL_HIP(hipMemcpyAsync(labels, m->conf_labels, (size_t)m->conf_tets * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, s));
+    if (xyz)
+        SAL_HIP(hipMemcpyAsync(xyz, m->conf_xyz, (size_t)m->conf_nodes * 3 * sizeof(float),
+                               hipMemcpyDeviceToDevice, s));
+    if (node_keys)
+        SAL_HIP(hipMemcpyAsync(node_keys, m->conf_keys, (size_t)m->conf_nodes * sizeof(int64_t),
+                               hipMemcpyDeviceToDevice, s));
+    return SAL_OK;
 }
 
 sal_status sal_tet_mesh_export(sal_context *ctx, const sal_tet_mesh *mc, uint64_t *keys,

@@ -16,36 +16,13 @@
 // parent cell).
 #include <hip/hip_runtime.h>
 
+#include "kuhn_dev.h"
 #include "mesh_internal.h"
 
 namespace sal {
 namespace {
 
-__device__ __forceinline__ void perm_of(int q, int &p0, int &p1, int &p2) {
-    // lexicographic permutations of (x, y, z)
-    p0 = q >> 1;
-    const int a = p0 == 0 ? 1 : 0;
-    const int b = p0 == 2 ? 1 : 2;
-    if (q & 1) { p1 = b; p2 = a; } else { p1 = a; p2 = b; }
-}
-
-__device__ __forceinline__ int q_of(int p0, int p1, int p2) { return 2 * p0 + (p1 > p2 ? 1 : 0); }
-
-__device__ __forceinline__ uint64_t make_key(int l, int q, int64_t i, int64_t j, int64_t k) {
-    return ((uint64_t)l << 60) | ((uint64_t)q << 57) | ((uint64_t)i << 38) | ((uint64_t)j << 19) |
-           (uint64_t)k;
-}
-
-__device__ __forceinline__ void split_key(uint64_t key, int &l, int &q, int64_t c[3]) {
-    l = (int)(key >> 60);
-    q = (int)((key >> 57) & 7u);
-    c[0] = (int64_t)((key >> 38) & 0x7ffffu);
-    c[1] = (int64_t)((key >> 19) & 0x7ffffu);
-    c[2] = (int64_t)(key & 0x7ffffu);
-}
-
-// Centroid in double, rounded once to float (no contraction: the value is
-// defined by the separately rounded product and sum).
+// Centroid: origin + h 2^-l (c + offset), each coordinate by lattice_coord.
 __device__ __forceinline__ void centroid(const LatticeGeom &g, int l, int q, const int64_t c[3],
                                          float &x, float &y, float &z) {
     int p0, p1, p2;
@@ -55,9 +32,9 @@ __device__ __forceinline__ void centroid(const LatticeGeom &g, int l, int q, con
     off[p1] = 0.5;
     off[p2] = 0.25;
     const double hl = ldexp(g.h, -l);
-    x = (float)__dadd_rn(g.origin[0], __dmul_rn(hl, (double)c[0] + off[0]));
-    y = (float)__dadd_rn(g.origin[1], __dmul_rn(hl, (double)c[1] + off[1]));
-    z = (float)__dadd_rn(g.origin[2], __dmul_rn(hl, (double)c[2] + off[2]));
+    x = lattice_coord(g.origin[0], hl, (double)c[0] + off[0]);
+    y = lattice_coord(g.origin[1], hl, (double)c[1] + off[1]);
+    z = lattice_coord(g.origin[2], hl, (double)c[2] + off[2]);
 }
 
 __global__ void k_lattice_centroids(LatticeGeom g, int64_t n0, float *__restrict__ cx,
@@ -72,18 +49,6 @@ __global__ void k_lattice_centroids(LatticeGeom g, int64_t n0, float *__restrict
     c[1] = cell % g.cells[1];
     c[2] = cell / g.cells[1];
     centroid(g, 0, q, c, cx[i], cy[i], cz[i]);
-}
-
-__device__ __forceinline__ uint64_t entry_key(const LevelPtrs &L, const LatticeGeom &g, int l,
-                                              int64_t i) {
-    if (l > 0) return L.key[l][i];
-    const int q = (int)(i % 6);
-    int64_t cell = i / 6;
-    const int64_t cx = cell % g.cells[0];
-    cell /= g.cells[0];
-    const int64_t cy = cell % g.cells[1];
-    const int64_t cz = cell / g.cells[1];
-    return make_key(0, q, cx, cy, cz);
 }
 
 // The leaf containing the level-l tetrahedron (c, q): its (level, index), or
@@ -294,7 +259,7 @@ __device__ void split_one(const LevelPtrs &L, const LatticeGeom &g, const ChildT
     const int64_t o = 8 * b + r;
     L.key[l + 1][o] = make_key(l + 1, cq, cc[0], cc[1], cc[2]);
     L.child[l + 1][o] = -1;
-    L.label[l + 1][o] = -2;
+    L.label[l + 1][o] = L.inherit ? L.label[l][i] : -2;
     if (cx) centroid(g, l + 1, cq, cc, cx[jj], cy[jj], cz[jj]);
 }
 
@@ -313,20 +278,6 @@ __global__ void k_split(LevelPtrs L, LatticeGeom g, ChildTables T, int l,
 // nodes added by a split (edge midpoints) carried per child tetrahedron as
 // the masks of its four vertices (x0..x3 in its own Kuhn order).
 
-// Vertices x0..x3 of (cell c, permutation q) in that level's integer units.
-__device__ __forceinline__ void kuhn_vertices(int q, const int64_t c[3], int64_t X[4][3]) {
-    int p0, p1, p2;
-    perm_of(q, p0, p1, p2);
-    for (int a = 0; a < 3; ++a) {
-        X[0][a] = c[a];
-        X[3][a] = c[a] + 1;
-    }
-    for (int a = 0; a < 3; ++a) X[1][a] = X[0][a];
-    X[1][p0] += 1;
-    for (int a = 0; a < 3; ++a) X[2][a] = X[1][a];
-    X[2][p1] += 1;
-}
-
 __device__ __forceinline__ int32_t mask_label(const SurfaceDev *surf, uint64_t m) {
     return m ? surf[63 - __builtin_clzll(m)].label : 0;
 }
@@ -337,9 +288,9 @@ __global__ void k_lattice_nodes(LatticeGeom g, int64_t n_nodes, float *__restric
     if (i >= n_nodes) return;
     const int64_t nx1 = g.cells[0] + 1, ny1 = g.cells[1] + 1;
     const int64_t u = i % nx1, v = (i / nx1) % ny1, w = i / (nx1 * ny1);
-    x[i] = (float)__dadd_rn(g.origin[0], __dmul_rn(g.h, (double)u));
-    y[i] = (float)__dadd_rn(g.origin[1], __dmul_rn(g.h, (double)v));
-    z[i] = (float)__dadd_rn(g.origin[2], __dmul_rn(g.h, (double)w));
+    x[i] = lattice_coord(g.origin[0], g.h, (double)u);
+    y[i] = lattice_coord(g.origin[1], g.h, (double)v);
+    z[i] = lattice_coord(g.origin[2], g.h, (double)w);
 }
 
 __device__ __forceinline__ int64_t node0_index(const LatticeGeom &g, const int64_t X[3]) {
@@ -386,7 +337,7 @@ __global__ void k_midpoints(LevelPtrs L, LatticeGeom g, int l, const int32_t *__
     const double hl = ldexp(g.h, -(l + 1));
     float *out[3] = {mx, my, mz};
     for (int a = 0; a < 3; ++a)
-        out[a][jj] = (float)__dadd_rn(g.origin[a], __dmul_rn(hl, (double)(X[ea[e]][a] + X[eb[e]][a])));
+        out[a][jj] = lattice_coord(g.origin[a], hl, (double)(X[ea[e]][a] + X[eb[e]][a]));
     // node key: coordinates on the level-kMaxLevels grid, 21 bits each
     const int sh = kMaxLevels - (l + 1);
     uint64_t key = 0;

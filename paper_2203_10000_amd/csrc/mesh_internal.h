@@ -19,6 +19,7 @@ struct LevelPtrs {
     uint8_t *flag[kMaxLevels + 1];
     int64_t n[kMaxLevels + 1];
     const int64_t *n_dev;   // device copy of the level sizes; when set it replaces n
+    int inherit;            // splits give the children their parent's label
 };
 
 // Per-round figures kept on the device by the captured refine round.
@@ -121,6 +122,31 @@ hipError_t launch_child_masks(const LevelPtrs &L, const LatticeGeom &g, int l,
                               const unsigned long long *mid_masks,
                               unsigned long long *vmask_child, const SurfaceDev *surf,
                               hipStream_t s);
+
+// Conforming transition refinement (conform.hip).
+hipError_t launch_insert_vertices(const LevelPtrs &L, const LatticeGeom &g, int l,
+                                  const int32_t *list, int64_t count, unsigned long long *tkeys,
+                                  int64_t cap, unsigned long long *overflow, hipStream_t s);
+hipError_t launch_leaf_pattern(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
+                               int64_t count, const unsigned long long *tkeys, int64_t cap,
+                               uint8_t *bits, hipStream_t s);
+hipError_t launch_tet_counts(const uint8_t *bits, int64_t count, int32_t *counts, hipStream_t s);
+// hipCUB device-wide primitives: with tmp == nullptr they only set *tmp_bytes.
+hipError_t exclusive_sum_i32(const int32_t *in, int64_t *out, int64_t n, void *tmp,
+                             size_t *tmp_bytes, hipStream_t s);
+hipError_t sort_keys_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
+                         hipStream_t s);
+hipError_t launch_emit(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
+                       int64_t count, const uint8_t *bits, const int64_t *offsets, int64_t *tets,
+                       int32_t *labels, hipStream_t s);
+// Distinct keys of a sorted array, in order; with tmp == nullptr it only sets
+// *tmp_bytes.
+hipError_t launch_unique(const int64_t *sorted, int64_t n, int32_t *head, int64_t *pos,
+                         int64_t *nodes, void *tmp, size_t *tmp_bytes, hipStream_t s);
+hipError_t launch_node_ids(const int64_t *tet_keys, int64_t n, const int64_t *nodes, int64_t n_nodes,
+                           int32_t *ids, hipStream_t s);
+hipError_t launch_node_xyz(const LatticeGeom &g, const int64_t *nodes, int64_t n, float *xyz,
+                           hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
