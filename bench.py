@@ -42,6 +42,8 @@ def parse():
                          "c5 precision stress: measurement lines for the design notes")
     ap.add_argument("--rule", default="centroid", choices=["centroid", "four_nodes"],
                     help="element rule of the c3 refine-and-relabel run")
+    ap.add_argument("--conform", action="store_true",
+                    help="c3: then build the conforming transition mesh and check it")
     ap.add_argument("--c5-lattice-fraction", type=float, default=0.125,
                     help="c5: fraction of the 0.5 mm lattice (a slab along z) to label")
     ap.add_argument("--check-sample", type=int, default=20000,
@@ -188,6 +190,48 @@ def _oracle_check_nodes(keys, lat, surfaces, gpu_labels_np, n, rng, near_mask=No
     return int((gpu_labels_np[idx] != want).sum()), int(len(idx))
 
 
+def _conform_c3(mesh, lat, rng, n_sample=200000):
+    """Conforming transition mesh of the refined c3 leaves, timed, with checks
+    that hold at any size: positive volumes that sum exactly to the box, and
+    no node at an edge midpoint of a sampled tetrahedron."""
+    import numpy as np
+    import torch
+    progress("c3: conforming transition mesh")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = mesh.conform()
+    wall = time.perf_counter() - t0
+    e = mesh.export_conforming()
+    keys = e["node_keys"]
+    m = 0x1FFFFF
+    pts = torch.stack([(keys >> 42) & m, (keys >> 21) & m, keys & m], 1)     # [n, 3] int64
+    tets = e["tets"].long()
+    v6 = torch.zeros(len(tets), dtype=torch.int64, device=tets.device)
+    for lo in range(0, len(tets), 1 << 24):
+        p = pts[tets[lo:lo + (1 << 24)]]
+        a, b, c = p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]
+        v6[lo:lo + len(p)] = (a[:, 0] * (b[:, 1] * c[:, 2] - b[:, 2] * c[:, 1])
+                              - a[:, 1] * (b[:, 0] * c[:, 2] - b[:, 2] * c[:, 0])
+                              + a[:, 2] * (b[:, 0] * c[:, 1] - b[:, 1] * c[:, 0]))
+    box6 = 6 * int(np.prod(np.array(lat.cells, dtype=np.int64) * 8))
+    idx = torch.from_numpy(rng.choice(len(tets), min(n_sample, len(tets)), replace=False)).to(tets.device)
+    p = pts[tets[idx]]
+    hanging = 0
+    for i, j in [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]:
+        s2 = p[:, i] + p[:, j]
+        ok = (s2 % 2 == 0).all(1)
+        mk = ((s2[:, 0] // 2) << 42) | ((s2[:, 1] // 2) << 21) | (s2[:, 2] // 2)
+        pos = torch.searchsorted(keys, mk).clamp(max=len(keys) - 1)
+        hanging += int((ok & (keys[pos] == mk)).sum())
+    torch.cuda.synchronize()
+    res = dict(info)
+    res.update({"wall_s": wall, "leaves_per_s": info["n_leaves"] / wall,
+                "volumes_positive": bool((v6 > 0).all()), "volume_sum_exact": int(v6.sum()) == box6,
+                "hanging_nodes_in_sample": hanging, "sample_tets": int(len(idx))})
+    del e, pts, tets, v6
+    return res
+
+
 def run_c3(args):
     """c3: 20 compartments (4 x 81,920 + 16 x 5,120 triangles), 1 mm lattice
     (48M centroids), two refine-and-relabel rounds in FP32 + recheck."""
@@ -222,7 +266,9 @@ def run_c3(args):
                                             near)
     else:
         mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, near)
+    out_conform = _conform_c3(mesh, lat, rng) if args.conform else None
     return {"workload": "c3", "rule": args.rule, "triangles": cfg.n_tri, "rounds": st,
+            "conform": out_conform,
             "leaves": n_leaves,
             "max_level": lv, "pairs": pairs, "wall_s": wall,
             "g_pairs_per_s": pairs / wall / 1e9,

@@ -19,6 +19,8 @@ namespace sal {
 namespace {
 
 constexpr uint64_t kEmpty = ~0ull;
+constexpr unsigned kDeep = 1u << 6;   // an edge has a node at a quarter point
+constexpr unsigned kRed = 1u << 7;    // pattern not split by the paper: split 1 -> 8
 
 // The four vertices of leaf (l, i) on the finest grid.
 __device__ __forceinline__ void leaf_fine_vertices(const LevelPtrs &L, const LatticeGeom &g, int l,
@@ -56,21 +58,45 @@ __device__ __forceinline__ bool set_find(const unsigned long long *tkeys, int64_
     return false;
 }
 
-__global__ void k_insert_vertices(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
-                                  int64_t count, unsigned long long *__restrict__ tkeys, int64_t cap,
-                                  unsigned long long *__restrict__ overflow) {
-    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (jj >= 4 * count) return;
-    int64_t F[4][3];
-    leaf_fine_vertices(L, g, l, list[jj >> 2], F);
-    const uint64_t key = fine_key(F[jj & 3]);
+// Inserts key; *added tells whether it was new.  False when the table is full.
+__device__ __forceinline__ bool set_insert(unsigned long long *tkeys, int64_t cap, uint64_t key,
+                                           bool *added) {
     uint64_t h = set_hash(key) & (uint64_t)(cap - 1);
     for (int64_t probe = 0; probe < cap; ++probe) {
         const unsigned long long prev = atomicCAS(&tkeys[h], kEmpty, key);
-        if (prev == kEmpty || prev == key) return;
+        if (prev == kEmpty || prev == key) {
+            if (added) *added = prev == kEmpty;
+            return true;
+        }
         h = (h + 1) & (uint64_t)(cap - 1);
     }
-    atomicAdd(overflow, 1ull);
+    return false;
+}
+
+// Inserts the vertices of entries [first, first + count) of level l (leaves
+// or not: an inner entry's vertices are those of its corner children).  Keys
+// that were not in the set are counted in *n_new and, when `fresh` is given,
+// also put in that second set (the vertices new in this closure round).
+__global__ void k_insert_range(LevelPtrs L, LatticeGeom g, int l, int64_t first, int64_t count,
+                               unsigned long long *__restrict__ set, int64_t cap,
+                               unsigned long long *__restrict__ fresh, int64_t fcap,
+                               unsigned long long *__restrict__ n_new,
+                               unsigned long long *__restrict__ overflow) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool added = false;
+    if (jj < 4 * count) {
+        int64_t F[4][3];
+        leaf_fine_vertices(L, g, l, first + (jj >> 2), F);
+        const uint64_t key = fine_key(F[jj & 3]);
+        if (set_insert(set, cap, key, &added)) {
+            if (added && fresh && !set_insert(fresh, fcap, key, nullptr)) atomicAdd(overflow, 1ull);
+        } else {
+            atomicAdd(overflow, 1ull);
+        }
+    }
+    // one counter update per wave
+    const unsigned long long mask = __ballot(added);
+    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(n_new, (unsigned long long)__popcll(mask));
 }
 
 constexpr int kEdgeA[6] = {0, 0, 0, 1, 1, 2};
@@ -86,43 +112,76 @@ __device__ __forceinline__ bool allowed_pattern(unsigned bits) {
     return __popc(verts) == 3;   // two edges sharing a vertex, or the edges of one face
 }
 
-// Hanging-edge bits of every listed leaf (in list order) and the red flag of
-// the leaves whose pattern the paper does not split.
-__global__ void k_leaf_pattern(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
-                               int64_t count, const unsigned long long *__restrict__ tkeys,
-                               int64_t cap, uint8_t *__restrict__ bits_out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= count) return;
-    const int64_t i = list[j];
-    int64_t F[4][3];
-    leaf_fine_vertices(L, g, l, i, F);
+// Hanging-edge bits (0-5) and the quarter-point flag (bit 6) of a level-l
+// leaf against a vertex set.
+__device__ __forceinline__ unsigned leaf_hits(const int64_t F[4][3], int l,
+                                              const unsigned long long *set, int64_t cap) {
     unsigned bits = 0;
-    bool deep = false;
     for (int e = 0; e < 6; ++e) {
         const int a = kEdgeA[e], b = kEdgeB[e];
         if (l < kMaxLevels) {
             int64_t m[3];
             for (int x = 0; x < 3; ++x) m[x] = (F[a][x] + F[b][x]) >> 1;
-            if (set_find(tkeys, cap, fine_key(m))) bits |= 1u << e;
+            if (set_find(set, cap, fine_key(m))) bits |= 1u << e;
         }
-        if (l + 2 <= kMaxLevels) {
+        if (l + 2 <= kMaxLevels && !(bits & kDeep)) {
             int64_t q1[3], q2[3];
             for (int x = 0; x < 3; ++x) {
                 q1[x] = (3 * F[a][x] + F[b][x]) >> 2;
                 q2[x] = (F[a][x] + 3 * F[b][x]) >> 2;
             }
-            deep |= set_find(tkeys, cap, fine_key(q1)) || set_find(tkeys, cap, fine_key(q2));
+            if (set_find(set, cap, fine_key(q1)) || set_find(set, cap, fine_key(q2))) bits |= kDeep;
         }
     }
-    bits_out[j] = (uint8_t)bits;
-    L.flag[l][i] = (deep || !allowed_pattern(bits)) ? 1 : 0;
+    return bits;
 }
 
-__global__ void k_tet_counts(const uint8_t *__restrict__ bits, int64_t count,
+__device__ __forceinline__ uint8_t with_red(unsigned f) {
+    return (uint8_t)(((f & kDeep) || !allowed_pattern(f & 63u)) ? f | kRed : f);
+}
+
+// Full pattern of entries [first, first + count) of level l against the
+// vertex set: flag = hanging bits | deep | red for a leaf, 0 for an inner
+// entry.
+__global__ void k_pattern_full(LevelPtrs L, LatticeGeom g, int l, int64_t first, int64_t count,
+                               const unsigned long long *__restrict__ set, int64_t cap) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const int64_t i = first + j;
+    if (L.child[l][i] >= 0) {
+        L.flag[l][i] = 0;
+        return;
+    }
+    int64_t F[4][3];
+    leaf_fine_vertices(L, g, l, i, F);
+    L.flag[l][i] = with_red(leaf_hits(F, l, set, cap));
+}
+
+// Update of entries [0, count) of level l after a closure round: the vertex
+// set only grows, so a leaf's new pattern is its old one plus what the
+// vertices added in this round (the `fresh` set) hit.  Entries split in the
+// round are inner now and lose their flag.
+__global__ void k_pattern_fresh(LevelPtrs L, LatticeGeom g, int l, int64_t count,
+                                const unsigned long long *__restrict__ fresh, int64_t fcap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint8_t old = L.flag[l][i];
+    if (L.child[l][i] >= 0) {
+        if (old) L.flag[l][i] = 0;
+        return;
+    }
+    int64_t F[4][3];
+    leaf_fine_vertices(L, g, l, i, F);
+    const unsigned f = old | leaf_hits(F, l, fresh, fcap);
+    if (f != old) L.flag[l][i] = with_red(f);
+}
+
+// Tetrahedra per listed leaf: one plus its number of hanging edges.
+__global__ void k_tet_counts(LevelPtrs L, int l, const int32_t *__restrict__ list, int64_t count,
                              int32_t *__restrict__ counts) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= count) return;
-    counts[j] = 1 + __popc((unsigned)bits[j]);
+    counts[j] = 1 + __popc((unsigned)L.flag[l][list[j]] & 63u);
 }
 
 __device__ __forceinline__ void put_tet(int64_t *__restrict__ out, int64_t slot, const int64_t a[3],
@@ -142,7 +201,7 @@ __device__ __forceinline__ void put_tet(int64_t *__restrict__ out, int64_t slot,
 
 // The tetrahedra of every listed leaf at offsets[j] (first output slot).
 __global__ void k_emit(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restrict__ list,
-                       int64_t count, const uint8_t *__restrict__ bits,
+                       int64_t count,
                        const int64_t *__restrict__ offsets, int64_t *__restrict__ tets,
                        int32_t *__restrict__ labels) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -150,7 +209,7 @@ __global__ void k_emit(LevelPtrs L, LatticeGeom g, int l, const int32_t *__restr
     const int64_t i = list[j];
     int64_t F[4][3];
     leaf_fine_vertices(L, g, l, i, F);
-    const unsigned b = bits[j];
+    const unsigned b = L.flag[l][i] & 63u;
     const int n = __popc(b);
     const int64_t o = offsets[j];
     const int32_t lab = L.label[l][i];
@@ -264,25 +323,35 @@ inline unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-hipError_t launch_insert_vertices(const LevelPtrs &L, const LatticeGeom &g, int l,
-                                  const int32_t *list, int64_t count, unsigned long long *tkeys,
-                                  int64_t cap, unsigned long long *overflow, hipStream_t s) {
+hipError_t launch_insert_range(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t first,
+                               int64_t count, unsigned long long *set, int64_t cap,
+                               unsigned long long *fresh, int64_t fcap, unsigned long long *n_new,
+                               unsigned long long *overflow, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    k_insert_vertices<<<grid_of(4 * count), 256, 0, s>>>(L, g, l, list, count, tkeys, cap, overflow);
+    k_insert_range<<<grid_of(4 * count), 256, 0, s>>>(L, g, l, first, count, set, cap, fresh, fcap,
+                                                      n_new, overflow);
     return hipGetLastError();
 }
 
-hipError_t launch_leaf_pattern(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
-                               int64_t count, const unsigned long long *tkeys, int64_t cap,
-                               uint8_t *bits, hipStream_t s) {
+hipError_t launch_pattern_full(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t first,
+                               int64_t count, const unsigned long long *set, int64_t cap,
+                               hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    k_leaf_pattern<<<grid_of(count), 256, 0, s>>>(L, g, l, list, count, tkeys, cap, bits);
+    k_pattern_full<<<grid_of(count), 256, 0, s>>>(L, g, l, first, count, set, cap);
     return hipGetLastError();
 }
 
-hipError_t launch_tet_counts(const uint8_t *bits, int64_t count, int32_t *counts, hipStream_t s) {
+hipError_t launch_pattern_fresh(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t count,
+                                const unsigned long long *fresh, int64_t fcap, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    k_tet_counts<<<grid_of(count), 256, 0, s>>>(bits, count, counts);
+    k_pattern_fresh<<<grid_of(count), 256, 0, s>>>(L, g, l, count, fresh, fcap);
+    return hipGetLastError();
+}
+
+hipError_t launch_tet_counts(const LevelPtrs &L, int l, const int32_t *list, int64_t count,
+                             int32_t *counts, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_tet_counts<<<grid_of(count), 256, 0, s>>>(L, l, list, count, counts);
     return hipGetLastError();
 }
 
@@ -292,10 +361,10 @@ hipError_t exclusive_sum_i32(const int32_t *in, int64_t *out, int64_t n, void *t
 }
 
 hipError_t launch_emit(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
-                       int64_t count, const uint8_t *bits, const int64_t *offsets, int64_t *tets,
-                       int32_t *labels, hipStream_t s) {
+                       int64_t count, const int64_t *offsets, int64_t *tets, int32_t *labels,
+                       hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    k_emit<<<grid_of(count), 256, 0, s>>>(L, g, l, list, count, bits, offsets, tets, labels);
+    k_emit<<<grid_of(count), 256, 0, s>>>(L, g, l, list, count, offsets, tets, labels);
     return hipGetLastError();
 }
 

@@ -139,7 +139,7 @@ sal_status ensure_level(sal_tet_mesh *m, int l, int64_t need, hipStream_t s) {
     if (l > 0 && (st = grow(&m->key[l], m->n[l], cap, s)) != SAL_OK) return st;
     if ((st = grow(&m->label[l], m->n[l], cap, s)) != SAL_OK) return st;
     if ((st = grow(&m->child[l], m->n[l], cap, s)) != SAL_OK) return st;
-    if ((st = grow(&m->flag[l], 0, cap, s)) != SAL_OK) return st;
+    if ((st = grow(&m->flag[l], m->n[l], cap, s)) != SAL_OK) return st;
     if (l > 0 && m->rule == SAL_RULE_FOUR_NODES &&
         (st = grow(&m->vmask[l], 4 * m->n[l], 4 * cap, s)) != SAL_OK)
         return st;
@@ -584,8 +584,10 @@ namespace {
 // Device scratch freed when the call ends.
 struct DevScratch {
     std::vector<void *> bufs;
-    ~DevScratch() {
+    ~DevScratch() { clear(); }
+    void clear() {
         for (void *p : bufs) (void)hipFree(p);
+        bufs.clear();
     }
     template <typename T>
     sal_status get(T **p, int64_t n) {
@@ -786,58 +788,51 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
         hipStream_t s = ctx->stream;
         sal_status st;
         DevScratch keep;                 // lives to the end of the call
-        uint8_t *bits = nullptr;         // hanging-edge bits of the listed leaves
-        int64_t count[kMaxLevels + 1], off[kMaxLevels + 2], n_all = 0;
+        unsigned long long *counters = nullptr;   // [0] keys added, [1] overflow
+        if ((st = keep.get(&counters, 2)) != SAL_OK) return st;
+        // closure state: flags per entry (hanging bits, quarter point, red)
+        // and the set of all vertices, built once and grown with the splits
+        int64_t entries = 0;
+        for (int l = 0; l <= m->max_level; ++l) entries += m->n[l];
+        int64_t cap = 1 << 16, used = 0;
+        while (cap < 2 * entries) cap <<= 1;
+        DevScratch set_mem;
+        unsigned long long *set = nullptr;
+        // (re)builds the set from every entry and the full patterns
+        auto rebuild = [&]() -> sal_status {
+            for (;;) {
+                set_mem.clear();
+                sal_status e;
+                if ((e = set_mem.get(&set, cap)) != SAL_OK) return e;
+                SAL_HIP(launch_fill_u64(set, ~0ull, cap, s));
+                SAL_HIP(launch_fill_u64(counters, 0ull, 2, s));
+                LevelPtrs L = ptrs(m);
+                for (int l = 0; l <= m->max_level; ++l)
+                    SAL_HIP(launch_insert_range(L, m->g, l, 0, m->n[l], set, cap, nullptr, 0,
+                                                counters, counters + 1, s));
+                unsigned long long c[2] = {0, 0};
+                SAL_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, s));
+                SAL_HIP(hipStreamSynchronize(s));
+                used = (int64_t)c[0];
+                if (c[1] == 0 && 2 * used <= cap) break;
+                cap <<= 2;
+            }
+            LevelPtrs L = ptrs(m);
+            for (int l = 0; l <= m->max_level; ++l)
+                SAL_HIP(launch_pattern_full(L, m->g, l, 0, m->n[l], set, cap, s));
+            return SAL_OK;
+        };
+        if ((st = rebuild()) != SAL_OK) return st;
         int rounds = 0;
         for (;;) {
             DevScratch iter;             // freed at the end of each closure round
-            // the leaves of every level, in index order
-            std::memset(count, 0, sizeof(count));
-            std::memset(off, 0, sizeof(off));
+            int64_t off[kMaxLevels + 2] = {0};
             for (int l = 0; l <= m->max_level; ++l) off[l + 1] = off[l] + m->n[l];
-            if ((st = ensure_buf(&m->list, &m->list_cap, off[m->max_level + 1], s)) != SAL_OK) return st;
-            for (int l = 0; l <= m->max_level; ++l) {
-                CompactSrc src{nullptr, m->child[l]};
-                if ((st = compact(m, src, m->n[l], m->list + off[l], m->totals + l, s)) != SAL_OK)
-                    return st;
-            }
-            SAL_HIP(hipMemcpyAsync(count, m->totals, sizeof(int64_t) * (m->max_level + 1),
-                                   hipMemcpyDeviceToHost, s));
-            SAL_HIP(hipStreamSynchronize(s));
-            n_all = 0;
-            for (int l = 0; l <= m->max_level; ++l) n_all += count[l];
-            if (n_all != m->n_leaves) return set_error(SAL_ERR_INTERNAL, "leaf count mismatch");
-            // the set of all leaf vertices (finest-grid keys); grown on overflow
-            int64_t cap = 1 << 16;
-            while (cap < 2 * n_all) cap <<= 1;
-            unsigned long long *set = nullptr, *overflow = nullptr;
-            if ((st = iter.get(&overflow, 1)) != SAL_OK) return st;
-            LevelPtrs L = ptrs(m);
-            for (;;) {
-                if ((st = iter.get(&set, cap)) != SAL_OK) return st;
-                SAL_HIP(launch_fill_u64(set, ~0ull, cap, s));
-                SAL_HIP(launch_fill_u64(overflow, 0ull, 1, s));
-                for (int l = 0; l <= m->max_level; ++l)
-                    SAL_HIP(launch_insert_vertices(L, m->g, l, m->list + off[l], count[l], set, cap,
-                                                   overflow, s));
-                unsigned long long over = 0;
-                SAL_HIP(hipMemcpyAsync(&over, overflow, sizeof(over), hipMemcpyDeviceToHost, s));
-                SAL_HIP(hipStreamSynchronize(s));
-                if (!over) break;
-                cap <<= 2;
-            }
-            // hanging patterns, and red flags on the leaves the paper does not split
-            if ((st = keep.get(&bits, n_all)) != SAL_OK) return st;
-            for (int l = 0; l <= m->max_level; ++l) SAL_HIP(launch_fill_u8(m->flag[l], 0, m->n[l], s));
-            int64_t boff = 0;
-            for (int l = 0; l <= m->max_level; boff += count[l], ++l)
-                SAL_HIP(launch_leaf_pattern(L, m->g, l, m->list + off[l], count[l], set, cap,
-                                            bits + boff, s));
             int32_t *red_list = nullptr;
             if ((st = iter.get(&red_list, off[m->max_level + 1])) != SAL_OK) return st;
             int64_t red[kMaxLevels + 1] = {0}, total_red = 0;
             for (int l = 0; l <= m->max_level; ++l) {
-                CompactSrc src{m->flag[l], nullptr};
+                CompactSrc src{m->flag[l], nullptr, 0x80};
                 if ((st = compact(m, src, m->n[l], red_list + off[l], m->totals + l, s)) != SAL_OK)
                     return st;
             }
@@ -850,6 +845,8 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
                 return set_error(SAL_ERR_INTERNAL, "closure beyond level 3");
             // red splits, deepest level first (its arrays never move under a
             // pending split of a coarser level); children keep the label
+            int64_t old_n[kMaxLevels + 1] = {0};
+            for (int l = 0; l <= kMaxLevels; ++l) old_n[l] = m->n[l];
             for (int l = m->max_level; l >= 0; --l) {
                 if (red[l] == 0) continue;
                 const int64_t kids = 8 * red[l];
@@ -863,16 +860,64 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
                 if (l + 1 > m->max_level) m->max_level = l + 1;
                 m->n_leaves += 7 * red[l];
             }
-            SAL_HIP(hipStreamSynchronize(s));
             ++rounds;
+            // the new vertices are edge midpoints of the split leaves (6 each)
+            int64_t fcap = 1024;
+            while (fcap < 12 * total_red) fcap <<= 1;
+            unsigned long long *fresh = nullptr;
+            if ((st = iter.get(&fresh, fcap)) != SAL_OK) return st;
+            SAL_HIP(launch_fill_u64(fresh, ~0ull, fcap, s));
+            SAL_HIP(launch_fill_u64(counters, 0ull, 2, s));
+            LevelPtrs L = ptrs(m);
+            for (int l = 0; l <= m->max_level; ++l)
+                SAL_HIP(launch_insert_range(L, m->g, l, old_n[l], m->n[l] - old_n[l], set, cap, fresh,
+                                            fcap, counters, counters + 1, s));
+            unsigned long long c[2] = {0, 0};
+            SAL_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, s));
+            SAL_HIP(hipStreamSynchronize(s));
+            used += (int64_t)c[0];
+            if (c[1] != 0 || 2 * used > cap) {
+                // a table filled up: a larger set and full patterns
+                while (cap < 4 * used) cap <<= 1;
+                if (c[1] != 0) cap <<= 1;
+                if ((st = rebuild()) != SAL_OK) return st;
+                SAL_HIP(hipStreamSynchronize(s));
+                continue;
+            }
+            // old entries: patterns plus what the new vertices hit; new
+            // children: full patterns
+            for (int l = 0; l <= m->max_level; ++l) {
+                SAL_HIP(launch_pattern_fresh(L, m->g, l, old_n[l], fresh, fcap, s));
+                SAL_HIP(launch_pattern_full(L, m->g, l, old_n[l], m->n[l] - old_n[l], set, cap, s));
+            }
+            SAL_HIP(hipStreamSynchronize(s));   // before this round's scratch is freed
         }
+
+        // the leaves in index order per level
+        int64_t count[kMaxLevels + 1] = {0}, off[kMaxLevels + 2] = {0}, n_all = 0;
+        for (int l = 0; l <= m->max_level; ++l) off[l + 1] = off[l] + m->n[l];
+        if ((st = ensure_buf(&m->list, &m->list_cap, off[m->max_level + 1], s)) != SAL_OK) return st;
+        for (int l = 0; l <= m->max_level; ++l) {
+            CompactSrc src{nullptr, m->child[l]};
+            if ((st = compact(m, src, m->n[l], m->list + off[l], m->totals + l, s)) != SAL_OK) return st;
+        }
+        SAL_HIP(hipMemcpyAsync(count, m->totals, sizeof(int64_t) * (m->max_level + 1),
+                               hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipStreamSynchronize(s));
+        for (int l = 0; l <= m->max_level; ++l) n_all += count[l];
+        if (n_all != m->n_leaves) return set_error(SAL_ERR_INTERNAL, "leaf count mismatch");
 
         // the tetrahedra of each leaf, at the exclusive sum of the counts
         int32_t *counts = nullptr;
         int64_t *offsets = nullptr;
         if ((st = keep.get(&counts, n_all)) != SAL_OK || (st = keep.get(&offsets, n_all)) != SAL_OK)
             return st;
-        SAL_HIP(launch_tet_counts(bits, n_all, counts, s));
+        {
+            LevelPtrs L = ptrs(m);
+            int64_t coff = 0;
+            for (int l = 0; l <= m->max_level; coff += count[l], ++l)
+                SAL_HIP(launch_tet_counts(L, l, m->list + off[l], count[l], counts + coff, s));
+        }
         size_t tmp_bytes = 0;
         SAL_HIP(exclusive_sum_i32(counts, offsets, n_all, nullptr, &tmp_bytes, s));
         char *tmp = nullptr;
@@ -900,8 +945,8 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
         LevelPtrs L = ptrs(m);
         int64_t boff = 0;
         for (int l = 0; l <= m->max_level; boff += count[l], ++l)
-            SAL_HIP(launch_emit(L, m->g, l, m->list + off[l], count[l], bits + boff, offsets + boff,
-                                tkeys, m->conf_labels, s));
+            SAL_HIP(launch_emit(L, m->g, l, m->list + off[l], count[l], offsets + boff, tkeys,
+                                m->conf_labels, s));
         // nodes: the distinct corner keys in ascending order; ids by search
         size_t sort_bytes = 0, uniq_bytes = 0;
         SAL_HIP(sort_keys_i64(tkeys, sorted, n_corner, nullptr, &sort_bytes, s));

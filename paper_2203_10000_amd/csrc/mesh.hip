@@ -147,7 +147,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 __device__ __forceinline__ bool pred(const CompactSrc &s, int64_t i) {
-    return s.flag ? s.flag[i] != 0 : s.child[i] < 0;
+    return s.flag ? (s.flag[i] & (s.mask ? s.mask : 0xffu)) != 0 : s.child[i] < 0;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_count(CompactSrc s, int64_t n,

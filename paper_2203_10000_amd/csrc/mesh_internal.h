@@ -59,8 +59,9 @@ struct ChildTables {
 
 // Source of a compaction: nonzero flags, or leaves (child < 0).
 struct CompactSrc {
-    const uint8_t *flag;
-    const int32_t *child;
+    const uint8_t *flag;    // entries with flag & mask != 0 (mask 0: any bit) ...
+    const int32_t *child;   // ... or, without flag, the leaves (child < 0)
+    uint8_t mask;
 };
 
 hipError_t launch_lattice_centroids(const LatticeGeom &g, int64_t n0, float *cx, float *cy,
@@ -124,21 +125,27 @@ hipError_t launch_child_masks(const LevelPtrs &L, const LatticeGeom &g, int l,
                               hipStream_t s);
 
 // Conforming transition refinement (conform.hip).
-hipError_t launch_insert_vertices(const LevelPtrs &L, const LatticeGeom &g, int l,
-                                  const int32_t *list, int64_t count, unsigned long long *tkeys,
-                                  int64_t cap, unsigned long long *overflow, hipStream_t s);
-hipError_t launch_leaf_pattern(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
-                               int64_t count, const unsigned long long *tkeys, int64_t cap,
-                               uint8_t *bits, hipStream_t s);
-hipError_t launch_tet_counts(const uint8_t *bits, int64_t count, int32_t *counts, hipStream_t s);
+// Flags of a leaf during the closure (in LevelPtrs::flag): bits 0-5 the
+// hanging edges, bit 6 a node at a quarter point, bit 7 split 1 -> 8.
+hipError_t launch_insert_range(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t first,
+                               int64_t count, unsigned long long *set, int64_t cap,
+                               unsigned long long *fresh, int64_t fcap, unsigned long long *n_new,
+                               unsigned long long *overflow, hipStream_t s);
+hipError_t launch_pattern_full(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t first,
+                               int64_t count, const unsigned long long *set, int64_t cap,
+                               hipStream_t s);
+hipError_t launch_pattern_fresh(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t count,
+                                const unsigned long long *fresh, int64_t fcap, hipStream_t s);
+hipError_t launch_tet_counts(const LevelPtrs &L, int l, const int32_t *list, int64_t count,
+                             int32_t *counts, hipStream_t s);
 // hipCUB device-wide primitives: with tmp == nullptr they only set *tmp_bytes.
 hipError_t exclusive_sum_i32(const int32_t *in, int64_t *out, int64_t n, void *tmp,
                              size_t *tmp_bytes, hipStream_t s);
 hipError_t sort_keys_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
                          hipStream_t s);
 hipError_t launch_emit(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
-                       int64_t count, const uint8_t *bits, const int64_t *offsets, int64_t *tets,
-                       int32_t *labels, hipStream_t s);
+                       int64_t count, const int64_t *offsets, int64_t *tets, int32_t *labels,
+                       hipStream_t s);
 // Distinct keys of a sorted array, in order; with tmp == nullptr it only sets
 // *tmp_bytes.
 hipError_t launch_unique(const int64_t *sorted, int64_t n, int32_t *head, int64_t *pos,
