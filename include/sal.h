@@ -313,6 +313,52 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *mesh, sal_confor
 sal_status sal_tet_mesh_export_conforming(sal_context *ctx, const sal_tet_mesh *mesh, int32_t *tets,
                                           int32_t *labels, float *xyz, int64_t *node_keys);
 
+/* ------------------------------------------------------- Taubin smoothing */
+typedef struct sal_smooth_params {
+    double lambda;            /* forward step, 0 < lambda < 1 (default 0.4) */
+    double mu;                /* backward step, 0 < mu < 1 (default 0.4) */
+    double xi_surface;        /* stopping ratio of the surface phase (0.1) */
+    double xi_volume;         /* stopping ratio of the volume phase (0.9) */
+    int32_t max_iter_surface; /* iteration caps (100 each); 0 skips a phase */
+    int32_t max_iter_volume;
+} sal_smooth_params;
+
+void sal_smooth_params_default(sal_smooth_params *p); /* section 3's values */
+
+typedef struct sal_smooth_info {
+    int64_t n_edges;          /* edges of the conforming mesh */
+    int64_t n_surface_edges;  /* edges whose tetrahedra carry two or more labels */
+    int64_t n_surface_nodes;  /* nodes moved by the surface phase */
+    int64_t n_volume_nodes;   /* nodes moved by the volume phase */
+    int32_t iters_surface, iters_volume;
+    double ratio_surface;     /* stopping ratio of each phase's last iteration */
+    double ratio_volume;
+    float ms_build;           /* edge graph and node classes (first call only) */
+    float ms_surface, ms_volume;
+    int32_t reserved;
+} sal_smooth_info;
+
+/* Section 2.2.1: Taubin smoothing of the conforming mesh's nodes, in place.
+ * One iteration is a forward and a backward half step over the nodes a
+ * phase moves,
+ *   x_i <- x_i + lambda (m_i - x_i),   then   x_i <- x_i - mu (m_i - x_i),
+ * m_i the mean position over node i and its neighbours (each half step reads
+ * the positions of the previous one).  The surface phase moves the nodes on
+ * an interface (an edge joining tetrahedra of two or more labels) along
+ * interface edges only; the volume phase then moves every other node along
+ * all edges.  Nodes on a face of the lattice box never move.  A phase stops
+ * after the first iteration k with ||x(k+1/2) - x(k)|| / ||x(0)|| <= xi
+ * (norms over the nodes it moves, x(0) their positions at the phase start)
+ * or after its iteration cap.  Positions are kept in float32 and each half
+ * step is computed in double.  The edge graph is built on the first call and
+ * kept on the mesh; later calls smooth the current positions again.
+ *   params  NULL for the defaults;  info  NULL, or filled
+ * Errors: SAL_ERR_INVALID_ARG before sal_tet_mesh_conform or for parameters
+ * outside (0, 1); SAL_ERR_CAPACITY above 2^28 nodes, 357M tetrahedra or
+ * labels outside [-1, 254]. */
+sal_status sal_tet_mesh_smooth(sal_context *ctx, sal_tet_mesh *mesh, const sal_smooth_params *params,
+                               sal_smooth_info *info);
+
 /* ------------------------------------------------------------ batched form
  * Many independent labeling problems in one persistent launch: the work is
  * cut into (instance, point block, surface, triangle range) items ordered by

@@ -88,6 +88,24 @@ class ConformInfo(ctypes.Structure):
         return d
 
 
+class SmoothParams(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("mu", ctypes.c_double),
+                ("xi_surface", ctypes.c_double), ("xi_volume", ctypes.c_double),
+                ("max_iter_surface", ctypes.c_int32), ("max_iter_volume", ctypes.c_int32)]
+
+
+class SmoothInfo(ctypes.Structure):
+    _fields_ = [("n_edges", ctypes.c_int64), ("n_surface_edges", ctypes.c_int64),
+                ("n_surface_nodes", ctypes.c_int64), ("n_volume_nodes", ctypes.c_int64),
+                ("iters_surface", ctypes.c_int32), ("iters_volume", ctypes.c_int32),
+                ("ratio_surface", ctypes.c_double), ("ratio_volume", ctypes.c_double),
+                ("ms_build", ctypes.c_float), ("ms_surface", ctypes.c_float),
+                ("ms_volume", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("surfaces", ctypes.c_void_p), ("n_points", ctypes.c_int64),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
@@ -124,6 +142,9 @@ _SIGNATURES = [
     ("sal_tet_mesh_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("sal_tet_mesh_conform", ctypes.c_int, [_P, _P, ctypes.POINTER(ConformInfo)]),
     ("sal_tet_mesh_export_conforming", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    ("sal_smooth_params_default", None, [ctypes.POINTER(SmoothParams)]),
+    ("sal_tet_mesh_smooth", ctypes.c_int,
+     [_P, _P, ctypes.POINTER(SmoothParams), ctypes.POINTER(SmoothInfo)]),
     ("sal_label_batch", ctypes.c_int,
      [_P, ctypes.POINTER(Instance), ctypes.c_int32, ctypes.POINTER(LabelOptions),
       ctypes.POINTER(LabelStats)]),
@@ -345,6 +366,21 @@ class TetMesh:
             self.ctx.handle, self.handle, _ptr(out["tets"]), _ptr(out["labels"]),
             _ptr(out["xyz"]), _ptr(out["node_keys"])))
         return out
+
+    def smooth(self, **params):
+        """sal_tet_mesh_smooth on the conforming mesh.  params: lam, mu,
+        xi_surface, xi_volume, max_iter_surface, max_iter_volume (defaults:
+        sal_smooth_params_default).  Returns the info as a dict."""
+        p = SmoothParams()
+        lib().sal_smooth_params_default(ctypes.byref(p))
+        for k, v in params.items():
+            if not hasattr(p, k):
+                raise TypeError("unknown smoothing parameter %r" % k)
+            setattr(p, k, v)
+        info = SmoothInfo()
+        _check(lib().sal_tet_mesh_smooth(self.ctx.handle, self.handle, ctypes.byref(p),
+                                         ctypes.byref(info)))
+        return info.as_dict()
 
     def close(self):
         if self.handle:

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "mesh_internal.h"
+#include "post_internal.h"
 #include "runtime.h"
 
 namespace sal {
@@ -63,6 +64,7 @@ struct sal_tet_mesh {
     int32_t *conf_labels = nullptr;  // [conf_tets]
     int64_t *conf_keys = nullptr;    // [conf_nodes] node keys, ascending
     float *conf_xyz = nullptr;       // [conf_nodes][3]
+    sal::SmoothCache *smooth = nullptr;   // edge graph for smoothing
     int64_t n_leaves = 0;
     // scratch
     float *cen[3] = {};
@@ -579,6 +581,23 @@ sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set
 using namespace sal;
 
 namespace sal {
+
+// The conforming mesh for the post-processing passes; null before
+// sal_tet_mesh_conform.
+bool conform_view(sal_tet_mesh *m, ConformView *v) {
+    if (!m || !m->conformed) return false;
+    v->g = m->g;
+    v->n_tets = m->conf_tets;
+    v->n_nodes = m->conf_nodes;
+    v->ids = m->conf_ids;
+    v->labels = m->conf_labels;
+    v->keys = m->conf_keys;
+    v->xyz = m->conf_xyz;
+    v->cache = &m->smooth;
+    return true;
+}
+int mesh_device(const sal_tet_mesh *m) { return m->device; }
+
 namespace {
 
 // Device scratch freed when the call ends.
@@ -621,6 +640,7 @@ void sal_tet_mesh_destroy(sal_tet_mesh *m) {
     if (m->blocks) (void)hipFree(m->blocks);
     if (m->totals) (void)hipFree(m->totals);
     if (m->lab_scratch) (void)hipFree(m->lab_scratch);
+    sal::smooth_cache_free(m->smooth);
     void *conf[] = {m->conf_ids, m->conf_labels, m->conf_keys, m->conf_xyz};
     for (void *p : conf)
         if (p) (void)hipFree(p);

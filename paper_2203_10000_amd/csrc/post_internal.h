@@ -1,0 +1,81 @@
+// Post-processing of the conforming mesh (paper section 2.2): shared state
+// and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mesh_internal.h"
+#include "sal.h"
+
+namespace sal {
+
+// The conforming mesh as the post-processing passes see it (device arrays
+// owned by the mesh).
+struct SmoothCache;
+struct ConformView {
+    LatticeGeom g;
+    int64_t n_tets, n_nodes;
+    const int32_t *ids;      // [n_tets][4]
+    const int32_t *labels;   // [n_tets]
+    const int64_t *keys;     // [n_nodes] finest-grid node keys, ascending
+    float *xyz;              // [n_nodes][3]
+    SmoothCache **cache;     // edge graph and node classes, built on first use
+};
+
+// Edge graph of the conforming mesh: rows in node order, neighbours in
+// ascending order; bit 31 of a column marks an interface edge (the
+// tetrahedra around it carry two or more labels).
+struct SmoothCache {
+    int64_t n_nodes = 0, n_edges = 0, n_surface_edges = 0;
+    int64_t *rowptr = nullptr;   // [n_nodes + 1]
+    uint32_t *cols = nullptr;    // [2 n_edges]
+    uint8_t *cls = nullptr;      // [n_nodes] 0 fixed, 1 interface, 2 volume
+    int32_t *list[2] = {};       // nodes of the surface and of the volume phase
+    int64_t n_list[2] = {};
+    float4 *pos[2] = {};         // [n_nodes] working positions (w unused)
+    double *partials = nullptr;  // per-block sums
+    int64_t partials_cap = 0;
+    double *sum = nullptr;       // [1]
+};
+void smooth_cache_free(SmoothCache *c);
+
+// Defined with the mesh: false when the mesh is not conforming yet.
+bool conform_view(sal_tet_mesh *m, ConformView *v);
+int mesh_device(const sal_tet_mesh *m);
+
+constexpr int kSmoothThreads = 256;
+
+// Edge graph construction.
+// *bad_labels counts tetrahedra with a label outside [-1, 254].
+hipError_t launch_edge_occurrences(const int32_t *ids, const int32_t *labels, int64_t n_tets,
+                                   uint64_t *keys, unsigned long long *bad_labels, hipStream_t s);
+hipError_t sort_keys_u64(const uint64_t *in, uint64_t *out, int64_t n, int end_bit, void *tmp,
+                         size_t *tmp_bytes, hipStream_t s);
+// Per sorted occurrence: 1 where its edge (key >> 8) starts.
+hipError_t launch_edge_heads(const uint64_t *keys, int64_t n, int32_t *head, hipStream_t s);
+hipError_t exclusive_sum_head(const int32_t *head, int64_t *pos, int64_t n, void *tmp,
+                              size_t *tmp_bytes, hipStream_t s);
+hipError_t launch_edge_directed(const uint64_t *keys, const int32_t *head, const int64_t *pos,
+                                int64_t n, int64_t n_edges, int64_t *start, uint64_t *dkeys,
+                                unsigned long long *n_surf, hipStream_t s);
+hipError_t launch_csr(const uint64_t *dkeys, int64_t n2, int64_t n_nodes, int64_t *rowptr,
+                      uint32_t *cols, hipStream_t s);
+hipError_t launch_node_class(const int64_t *rowptr, const uint32_t *cols, const int64_t *keys,
+                             int64_t n_nodes, const LatticeGeom &g, uint8_t *cls, hipStream_t s);
+
+// Iterations.
+hipError_t launch_pack_pos(const float *xyz, int64_t n, float4 *a, float4 *b, hipStream_t s);
+hipError_t launch_unpack_pos(const float4 *p, int64_t n, float *xyz, hipStream_t s);
+// sum of |p_i|^2 over the list (block partials, then one fixed-order sum)
+hipError_t launch_norm_sq(const float4 *p, const int32_t *list, int64_t n, double *partials,
+                          double *sum, hipStream_t s);
+// out_i = in_i + coef (m_i - in_i) over the listed nodes, m_i the mean of in
+// over node i and its neighbours (interface edges only when surface_only);
+// *sum = sum of |out_i - in_i|^2.
+hipError_t launch_taubin_half(const float4 *in, float4 *out, const int64_t *rowptr,
+                              const uint32_t *cols, const int32_t *list, int64_t n, double coef,
+                              int surface_only, double *partials, double *sum, hipStream_t s);
+int64_t smooth_blocks(int64_t n);
+
+}  // namespace sal

@@ -1,0 +1,282 @@
+// Taubin smoothing of the conforming mesh (paper section 2.2.1): the edge
+// graph, the node classes and the half steps.
+//
+// Each half step is a sparse gather: per moved node, its row of neighbour
+// ids and their positions (float4, one 16-byte load each), the mean over the
+// node and its neighbours in double, and one position written back.  It is
+// bound by memory traffic; the arithmetic is a few double operations per
+// neighbour.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "post_internal.h"
+
+namespace sal {
+namespace {
+
+constexpr int kEdgeA[6] = {0, 0, 0, 1, 1, 2};
+constexpr int kEdgeB[6] = {1, 2, 3, 2, 3, 3};
+constexpr uint32_t kSurfBit = 1u << 31;
+
+inline unsigned grid_of(int64_t n) { return (unsigned)((n + kSmoothThreads - 1) / kSmoothThreads); }
+
+// Occurrence of edge e of tetrahedron t: (low id << 36) | (high id << 8) |
+// (label + 1), ids below 2^28 and labels in [-1, 254] (checked by the host).
+__global__ void k_edge_occurrences(const int32_t *__restrict__ ids, const int32_t *__restrict__ labels,
+                                   int64_t n_tets, uint64_t *__restrict__ keys,
+                                   unsigned long long *__restrict__ bad_labels) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= 6 * n_tets) return;
+    const int64_t t = jj / 6;
+    const int e = (int)(jj - 6 * t);
+    const uint32_t a = (uint32_t)ids[4 * t + kEdgeA[e]], b = (uint32_t)ids[4 * t + kEdgeB[e]];
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    const int32_t lab = labels[t];
+    if (e == 0 && (lab < -1 || lab > 254)) atomicAdd(bad_labels, 1ull);
+    keys[jj] = (lo << 36) | (hi << 8) | (uint64_t)(uint8_t)(lab + 1);
+}
+
+__global__ void k_edge_heads(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ head) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    head[i] = (i == 0 || (keys[i] >> 8) != (keys[i - 1] >> 8)) ? 1 : 0;
+}
+
+__global__ void k_edge_starts(const int32_t *__restrict__ head, const int64_t *__restrict__ pos,
+                              int64_t n, int64_t *__restrict__ start) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !head[i]) return;
+    start[pos[i]] = i;
+}
+
+// Both directions of edge e: (row << 32) | (col << 1) | interface, where the
+// edge is an interface edge when its occurrences carry different labels
+// (sorted, so the first and the last differ).
+__global__ void k_edge_emit(const uint64_t *__restrict__ keys, const int64_t *__restrict__ start,
+                            int64_t n, int64_t n_edges, uint64_t *__restrict__ dkeys,
+                            unsigned long long *__restrict__ n_surf) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t surf = 0;
+    if (e < n_edges) {
+        const int64_t s = start[e];
+        const int64_t last = (e + 1 < n_edges ? start[e + 1] : n) - 1;
+        const uint64_t k = keys[s];
+        surf = (k & 0xffu) != (keys[last] & 0xffu) ? 1u : 0u;
+        const uint64_t a = k >> 36, b = (k >> 8) & ((1ull << 28) - 1);
+        dkeys[2 * e] = (a << 32) | (b << 1) | surf;
+        dkeys[2 * e + 1] = (b << 32) | (a << 1) | surf;
+    }
+    const unsigned long long m = __ballot(surf != 0);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_surf, (unsigned long long)__popcll(m));
+}
+
+// Row pointers from the sorted directed keys (rows without an entry get an
+// empty range) and the columns with the interface bit.
+__global__ void k_csr(const uint64_t *__restrict__ dkeys, int64_t n2, int64_t n_nodes,
+                      int64_t *__restrict__ rowptr, uint32_t *__restrict__ cols) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n2) return;
+    const uint64_t d = dkeys[k];
+    const int64_t r = (int64_t)(d >> 32);
+    cols[k] = (uint32_t)((d >> 1) & 0x7fffffffu) | ((d & 1u) ? kSurfBit : 0u);
+    const int64_t prev = k == 0 ? -1 : (int64_t)(dkeys[k - 1] >> 32);
+    for (int64_t q = prev + 1; q <= r; ++q) rowptr[q] = k;
+    if (k == n2 - 1)
+        for (int64_t q = r + 1; q <= n_nodes; ++q) rowptr[q] = n2;
+}
+
+// 0: on a face of the lattice box (never moves); 1: on an interface
+// (surface phase); 2: any other node (volume phase).
+__global__ void k_node_class(const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ cols,
+                             const int64_t *__restrict__ keys, int64_t n, LatticeGeom g,
+                             uint8_t *__restrict__ cls) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = (uint64_t)keys[i];
+    const int64_t f[3] = {(int64_t)((k >> 42) & 0x1fffffu), (int64_t)((k >> 21) & 0x1fffffu),
+                          (int64_t)(k & 0x1fffffu)};
+    bool box = false;
+    for (int a = 0; a < 3; ++a) box |= f[a] == 0 || f[a] == ((int64_t)g.cells[a] << kMaxLevels);
+    bool surf = false;
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) surf |= (cols[q] & kSurfBit) != 0;
+    cls[i] = box ? 0 : (surf ? 1 : 2);
+}
+
+__global__ void k_pack_pos(const float *__restrict__ xyz, int64_t n, float4 *__restrict__ a,
+                           float4 *__restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 p = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], 0.0f);
+    a[i] = p;
+    b[i] = p;
+}
+
+__global__ void k_unpack_pos(const float4 *__restrict__ p, int64_t n, float *__restrict__ xyz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 q = p[i];
+    xyz[3 * i] = q.x;
+    xyz[3 * i + 1] = q.y;
+    xyz[3 * i + 2] = q.z;
+}
+
+// Fixed-order block sum of one double per thread into partials[blockIdx.x].
+__device__ __forceinline__ void block_sum(double v, double *partials) {
+    __shared__ double red[kSmoothThreads];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kSmoothThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kSmoothThreads) void k_norm_sq(const float4 *__restrict__ p,
+                                                           const int32_t *__restrict__ list,
+                                                           int64_t n, double *__restrict__ partials) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (t < n) {
+        const float4 q = p[list[t]];
+        v = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z;
+    }
+    block_sum(v, partials);
+}
+
+// One block: thread j sums partials j, j + 1024, ... in order, then a tree.
+__global__ __launch_bounds__(1024) void k_sum_partials(const double *__restrict__ partials, int64_t nb,
+                                                       double *__restrict__ out) {
+    __shared__ double red[1024];
+    double v = 0.0;
+    for (int64_t j = threadIdx.x; j < nb; j += 1024) v += partials[j];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ __launch_bounds__(kSmoothThreads) void k_taubin_half(
+    const float4 *__restrict__ in, float4 *__restrict__ out, const int64_t *__restrict__ rowptr,
+    const uint32_t *__restrict__ cols, const int32_t *__restrict__ list, int64_t n, double coef,
+    int surface_only, double *__restrict__ partials) {
+#pragma clang fp contract(off)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0;
+    if (t < n) {
+        const int32_t i = list[t];
+        const float4 xi = in[i];
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        int cnt = 0;
+        const uint32_t need = surface_only ? kSurfBit : 0u;
+        for (int64_t q = rowptr[i], end = rowptr[i + 1]; q < end; ++q) {
+            const uint32_t c = cols[q];
+            if ((c & need) != need) continue;
+            const float4 p = in[c & ~kSurfBit];
+            sx += (double)p.x;
+            sy += (double)p.y;
+            sz += (double)p.z;
+            ++cnt;
+        }
+        // mean over the node and its neighbours, then the step toward it
+        const double inv = (double)(cnt + 1);
+        const double mx = (sx + (double)xi.x) / inv, my = (sy + (double)xi.y) / inv,
+                     mz = (sz + (double)xi.z) / inv;
+        float4 o;
+        o.x = (float)((double)xi.x + coef * (mx - (double)xi.x));
+        o.y = (float)((double)xi.y + coef * (my - (double)xi.y));
+        o.z = (float)((double)xi.z + coef * (mz - (double)xi.z));
+        o.w = 0.0f;
+        out[i] = o;
+        const double dx = (double)o.x - xi.x, dy = (double)o.y - xi.y, dz = (double)o.z - xi.z;
+        d2 = dx * dx + dy * dy + dz * dz;
+    }
+    block_sum(d2, partials);
+}
+
+}  // namespace
+
+int64_t smooth_blocks(int64_t n) { return (n + kSmoothThreads - 1) / kSmoothThreads; }
+
+hipError_t launch_edge_occurrences(const int32_t *ids, const int32_t *labels, int64_t n_tets,
+                                   uint64_t *keys, unsigned long long *bad_labels, hipStream_t s) {
+    if (n_tets <= 0) return hipSuccess;
+    k_edge_occurrences<<<grid_of(6 * n_tets), kSmoothThreads, 0, s>>>(ids, labels, n_tets, keys,
+                                                                       bad_labels);
+    return hipGetLastError();
+}
+
+hipError_t sort_keys_u64(const uint64_t *in, uint64_t *out, int64_t n, int end_bit, void *tmp,
+                         size_t *tmp_bytes, hipStream_t s) {
+    return hipcub::DeviceRadixSort::SortKeys(tmp, *tmp_bytes, in, out, (int)n, 0, end_bit, s);
+}
+
+hipError_t launch_edge_heads(const uint64_t *keys, int64_t n, int32_t *head, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_edge_heads<<<grid_of(n), kSmoothThreads, 0, s>>>(keys, n, head);
+    return hipGetLastError();
+}
+
+hipError_t exclusive_sum_head(const int32_t *head, int64_t *pos, int64_t n, void *tmp,
+                              size_t *tmp_bytes, hipStream_t s) {
+    return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, head, pos, (int)n, s);
+}
+
+hipError_t launch_edge_directed(const uint64_t *keys, const int32_t *head, const int64_t *pos,
+                                int64_t n, int64_t n_edges, int64_t *start, uint64_t *dkeys,
+                                unsigned long long *n_surf, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_edge_starts<<<grid_of(n), kSmoothThreads, 0, s>>>(head, pos, n, start);
+    k_edge_emit<<<grid_of(n_edges), kSmoothThreads, 0, s>>>(keys, start, n, n_edges, dkeys, n_surf);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr(const uint64_t *dkeys, int64_t n2, int64_t n_nodes, int64_t *rowptr,
+                      uint32_t *cols, hipStream_t s) {
+    if (n2 <= 0) return hipSuccess;
+    k_csr<<<grid_of(n2), kSmoothThreads, 0, s>>>(dkeys, n2, n_nodes, rowptr, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_class(const int64_t *rowptr, const uint32_t *cols, const int64_t *keys,
+                             int64_t n_nodes, const LatticeGeom &g, uint8_t *cls, hipStream_t s) {
+    if (n_nodes <= 0) return hipSuccess;
+    k_node_class<<<grid_of(n_nodes), kSmoothThreads, 0, s>>>(rowptr, cols, keys, n_nodes, g, cls);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_pos(const float *xyz, int64_t n, float4 *a, float4 *b, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_pack_pos<<<grid_of(n), kSmoothThreads, 0, s>>>(xyz, n, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_pos(const float4 *p, int64_t n, float *xyz, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_unpack_pos<<<grid_of(n), kSmoothThreads, 0, s>>>(p, n, xyz);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_sq(const float4 *p, const int32_t *list, int64_t n, double *partials,
+                          double *sum, hipStream_t s) {
+    const int64_t nb = smooth_blocks(n);
+    if (nb > 0) k_norm_sq<<<(unsigned)nb, kSmoothThreads, 0, s>>>(p, list, n, partials);
+    k_sum_partials<<<1, 1024, 0, s>>>(partials, nb, sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_taubin_half(const float4 *in, float4 *out, const int64_t *rowptr,
+                              const uint32_t *cols, const int32_t *list, int64_t n, double coef,
+                              int surface_only, double *partials, double *sum, hipStream_t s) {
+    const int64_t nb = smooth_blocks(n);
+    if (nb > 0)
+        k_taubin_half<<<(unsigned)nb, kSmoothThreads, 0, s>>>(in, out, rowptr, cols, list, n, coef,
+                                                              surface_only, partials);
+    k_sum_partials<<<1, 1024, 0, s>>>(partials, nb, sum);
+    return hipGetLastError();
+}
+
+}  // namespace sal
