@@ -44,6 +44,10 @@ def parse():
                     help="element rule of the c3 refine-and-relabel run")
     ap.add_argument("--conform", action="store_true",
                     help="c3: then build the conforming transition mesh and check it")
+    ap.add_argument("--smooth", action="store_true",
+                    help="c3: conforming mesh, then Taubin smoothing (implies --conform)")
+    ap.add_argument("--smooth-iters", type=int, default=10,
+                    help="iterations per phase of the fixed-count smoothing run")
     ap.add_argument("--c5-lattice-fraction", type=float, default=0.125,
                     help="c5: fraction of the 0.5 mm lattice (a slab along z) to label")
     ap.add_argument("--check-sample", type=int, default=20000,
@@ -232,6 +236,36 @@ def _conform_c3(mesh, lat, rng, n_sample=200000):
     return res
 
 
+def _smooth_c3(mesh, iters):
+    """Taubin smoothing of the c3 conforming mesh: once with the paper's
+    parameters (edge graph built on this call), then `iters` iterations per
+    phase with the stopping rule off, timed per half step.  Bytes per half
+    step: every array read or written once (node list 4, row pointer 8,
+    columns 4 per entry, positions 16 per node read, 16 per node written)."""
+    import torch
+    progress("c3: Taubin smoothing")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    paper = mesh.smooth()
+    wall = time.perf_counter() - t0
+    fixed = mesh.smooth(xi_surface=-1.0, xi_volume=-1.0, max_iter_surface=iters,
+                        max_iter_volume=iters)
+    n_nodes = mesh.conform_info["n_nodes"]
+    out = {"paper_params": paper, "paper_params_wall_s": wall, "fixed_iterations": fixed}
+    for ph in ("surface", "volume"):
+        n = fixed["n_%s_nodes" % ph]
+        ent = fixed["n_entries_%s" % ph]
+        halves = 2 * fixed["iters_%s" % ph]
+        if not halves:
+            continue
+        ms = fixed["ms_%s" % ph] / halves
+        nbytes = 4 * n + 8 * n + 4 * ent + 16 * min(n_nodes, n + ent) + 16 * n
+        out["%s_half_step" % ph] = {"ms": ms, "nodes": n, "entries": ent, "bytes": nbytes,
+                                    "gb_per_s": nbytes / (ms * 1e-3) / 1e9,
+                                    "frac_of_8tb": nbytes / (ms * 1e-3) / 8e12}
+    return out
+
+
 def run_c3(args):
     """c3: 20 compartments (4 x 81,920 + 16 x 5,120 triangles), 1 mm lattice
     (48M centroids), two refine-and-relabel rounds in FP32 + recheck."""
@@ -266,9 +300,10 @@ def run_c3(args):
                                             near)
     else:
         mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, near)
-    out_conform = _conform_c3(mesh, lat, rng) if args.conform else None
+    out_conform = _conform_c3(mesh, lat, rng) if (args.conform or args.smooth) else None
+    out_smooth = _smooth_c3(mesh, args.smooth_iters) if args.smooth else None
     return {"workload": "c3", "rule": args.rule, "triangles": cfg.n_tri, "rounds": st,
-            "conform": out_conform,
+            "conform": out_conform, "smooth": out_smooth,
             "leaves": n_leaves,
             "max_level": lv, "pairs": pairs, "wall_s": wall,
             "g_pairs_per_s": pairs / wall / 1e9,

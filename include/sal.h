@@ -336,6 +336,8 @@ typedef struct sal_smooth_info {
     float ms_build;           /* edge graph and node classes (first call only) */
     float ms_surface, ms_volume;
     int32_t reserved;
+    int64_t n_entries_surface; /* neighbour entries one half step reads */
+    int64_t n_entries_volume;  /* (interface rows read whole in the surface phase) */
 } sal_smooth_info;
 
 /* Section 2.2.1: Taubin smoothing of the conforming mesh's nodes, in place.

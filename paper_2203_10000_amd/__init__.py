@@ -100,7 +100,8 @@ class SmoothInfo(ctypes.Structure):
                 ("iters_surface", ctypes.c_int32), ("iters_volume", ctypes.c_int32),
                 ("ratio_surface", ctypes.c_double), ("ratio_volume", ctypes.c_double),
                 ("ms_build", ctypes.c_float), ("ms_surface", ctypes.c_float),
-                ("ms_volume", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("ms_volume", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("n_entries_surface", ctypes.c_int64), ("n_entries_volume", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

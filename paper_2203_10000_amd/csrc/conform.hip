@@ -94,9 +94,14 @@ __global__ void k_insert_range(LevelPtrs L, LatticeGeom g, int l, int64_t first,
             atomicAdd(overflow, 1ull);
         }
     }
-    // one counter update per wave
+    // one counter update per block
+    __shared__ unsigned int block_new;
+    if (threadIdx.x == 0) block_new = 0;
+    __syncthreads();
     const unsigned long long mask = __ballot(added);
-    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(n_new, (unsigned long long)__popcll(mask));
+    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&block_new, (unsigned int)__popcll(mask));
+    __syncthreads();
+    if (threadIdx.x == 0 && block_new) atomicAdd(n_new, (unsigned long long)block_new);
 }
 
 constexpr int kEdgeA[6] = {0, 0, 0, 1, 1, 2};

@@ -23,16 +23,21 @@ struct ConformView {
     SmoothCache **cache;     // edge graph and node classes, built on first use
 };
 
-// Edge graph of the conforming mesh: rows in node order, neighbours in
-// ascending order; bit 31 of a column marks an interface edge (the
-// tetrahedra around it carry two or more labels).
+// Edge graph of the conforming mesh over the nodes renumbered in Morton
+// order (rank r is node order[r]): rows by rank, neighbours by ascending
+// rank; bit 31 of a column marks an interface edge (the tetrahedra around
+// it carry two or more labels).  Lists, row segments and working positions
+// are in rank space too.
 struct SmoothCache {
     int64_t n_nodes = 0, n_edges = 0, n_surface_edges = 0;
     int64_t *rowptr = nullptr;   // [n_nodes + 1]
     uint32_t *cols = nullptr;    // [2 n_edges]
     uint8_t *cls = nullptr;      // [n_nodes] 0 fixed, 1 interface, 2 volume
+    int32_t *order = nullptr;    // [n_nodes] node id of each Morton rank
     int32_t *list[2] = {};       // nodes of the surface and of the volume phase
+    uint64_t *seg[2] = {};       // their row segments
     int64_t n_list[2] = {};
+    int64_t n_entries[2] = {};   // row entries read per half step of each phase
     float4 *pos[2] = {};         // [n_nodes] working positions (w unused)
     double *partials = nullptr;  // per-block sums
     int64_t partials_cap = 0;
@@ -45,6 +50,14 @@ bool conform_view(sal_tet_mesh *m, ConformView *v);
 int mesh_device(const sal_tet_mesh *m);
 
 constexpr int kSmoothThreads = 256;
+#ifndef SAL_TAUBIN_GROUP
+#define SAL_TAUBIN_GROUP 2
+#endif
+#ifndef SAL_TAUBIN_UNROLL
+#define SAL_TAUBIN_UNROLL 8
+#endif
+constexpr int kTaubinGroup = SAL_TAUBIN_GROUP;     // lanes per node in a half step (power of 2)
+constexpr int kTaubinUnroll = SAL_TAUBIN_UNROLL;   // entries per lane loaded together
 
 // Edge graph construction.
 // *bad_labels counts tetrahedra with a label outside [-1, 254].
@@ -57,25 +70,40 @@ hipError_t launch_edge_heads(const uint64_t *keys, int64_t n, int32_t *head, hip
 hipError_t exclusive_sum_head(const int32_t *head, int64_t *pos, int64_t n, void *tmp,
                               size_t *tmp_bytes, hipStream_t s);
 hipError_t launch_edge_directed(const uint64_t *keys, const int32_t *head, const int64_t *pos,
-                                int64_t n, int64_t n_edges, int64_t *start, uint64_t *dkeys,
-                                unsigned long long *n_surf, hipStream_t s);
+                                int64_t n, int64_t n_edges, int64_t *start, const int32_t *rank,
+                                uint64_t *dkeys, unsigned long long *n_surf, hipStream_t s);
+// order[r]: the node of Morton rank r; rank[i]: the rank of node i.  With
+// tmp == nullptr it only sets *tmp_bytes.
+hipError_t launch_morton_order(const int64_t *keys, int64_t n, uint64_t *code, uint64_t *code_sorted,
+                               int32_t *ids, int32_t *order, int32_t *rank, void *tmp,
+                               size_t *tmp_bytes, hipStream_t s);
 hipError_t launch_csr(const uint64_t *dkeys, int64_t n2, int64_t n_nodes, int64_t *rowptr,
                       uint32_t *cols, hipStream_t s);
 hipError_t launch_node_class(const int64_t *rowptr, const uint32_t *cols, const int64_t *keys,
-                             int64_t n_nodes, const LatticeGeom &g, uint8_t *cls, hipStream_t s);
+                             const int32_t *order, int64_t n_nodes, const LatticeGeom &g, uint8_t *cls,
+                             hipStream_t s);
 
 // Iterations.
-hipError_t launch_pack_pos(const float *xyz, int64_t n, float4 *a, float4 *b, hipStream_t s);
-hipError_t launch_unpack_pos(const float4 *p, int64_t n, float *xyz, hipStream_t s);
+hipError_t launch_pack_pos(const float *xyz, const int32_t *order, int64_t n, float4 *a, float4 *b,
+                           hipStream_t s);
+hipError_t launch_unpack_pos(const float4 *p, const int32_t *order, int64_t n, float *xyz,
+                             hipStream_t s);
 // sum of |p_i|^2 over the list (block partials, then one fixed-order sum)
 hipError_t launch_norm_sq(const float4 *p, const int32_t *list, int64_t n, double *partials,
                           double *sum, hipStream_t s);
+// sum of the row lengths of the listed nodes
+hipError_t launch_row_entries(const int64_t *rowptr, const int32_t *list, int64_t n, double *partials,
+                              double *sum, hipStream_t s);
 // out_i = in_i + coef (m_i - in_i) over the listed nodes, m_i the mean of in
 // over node i and its neighbours (interface edges only when surface_only);
 // *sum = sum of |out_i - in_i|^2.
-hipError_t launch_taubin_half(const float4 *in, float4 *out, const int64_t *rowptr,
+hipError_t launch_taubin_half(const float4 *in, float4 *out, const uint64_t *seg,
                               const uint32_t *cols, const int32_t *list, int64_t n, double coef,
                               int surface_only, double *partials, double *sum, hipStream_t s);
-int64_t smooth_blocks(int64_t n);
+// seg[t] = (rowptr[list[t]] << 32) | row length (rows below 2^32 entries)
+hipError_t launch_row_segments(const int64_t *rowptr, const int32_t *list, int64_t n, uint64_t *seg,
+                               hipStream_t s);
+int64_t smooth_blocks(int64_t n);   // blocks of the one-thread-per-item kernels
+int64_t taubin_blocks(int64_t n);   // blocks of a half step over n nodes
 
 }  // namespace sal

@@ -1,6 +1,7 @@
 // Taubin smoothing of the conforming mesh (paper section 2.2.1): host side.
-// The edge graph is built once per conforming mesh with two radix sorts (edge
-// occurrences, then both directions of each distinct edge); the phases then
+// The edge graph is built once per conforming mesh with radix sorts (edge
+// occurrences; the nodes by Morton code; both directions of each distinct
+// edge in Morton ranks); the phases then
 // run half steps until the stopping ratio is met, reading one double back
 // per iteration.
 #include <algorithm>
@@ -15,8 +16,8 @@ namespace sal {
 
 void smooth_cache_free(SmoothCache *c) {
     if (!c) return;
-    void *p[] = {c->rowptr, c->cols, c->cls, c->list[0], c->list[1], c->pos[0], c->pos[1],
-                 c->partials, c->sum};
+    void *p[] = {c->rowptr, c->cols, c->cls, c->order, c->list[0], c->list[1], c->seg[0], c->seg[1],
+                 c->pos[0], c->pos[1], c->partials, c->sum};
     for (void *q : p)
         if (q) (void)hipFree(q);
     delete c;
@@ -93,7 +94,19 @@ sal_status build_graph(const ConformView &v, SmoothCache *c, hipStream_t s) {
     if ((st = t.get(&start, n_edges)) != SAL_OK || (st = t.get(&dkeys, n2)) != SAL_OK ||
         (st = t.get(&dsorted, n2)) != SAL_OK)
         return st;
-    SAL_HIP(launch_edge_directed(occ_sorted, head, pos, n_occ, n_edges, start, dkeys, cnt + 1, s));
+    // Morton ranks of the nodes
+    uint64_t *code = nullptr, *code_sorted = nullptr;
+    int32_t *ids = nullptr, *rank = nullptr;
+    if ((st = t.get(&code, v.n_nodes)) != SAL_OK || (st = t.get(&code_sorted, v.n_nodes)) != SAL_OK ||
+        (st = t.get(&ids, v.n_nodes)) != SAL_OK || (st = t.get(&rank, v.n_nodes)) != SAL_OK ||
+        (st = dev_alloc(&c->order, v.n_nodes)) != SAL_OK)
+        return st;
+    size_t bm = 0;
+    SAL_HIP(launch_morton_order(v.keys, v.n_nodes, code, code_sorted, ids, c->order, rank, nullptr, &bm, s));
+    char *tmpm = nullptr;
+    if ((st = t.get(&tmpm, (int64_t)bm)) != SAL_OK) return st;
+    SAL_HIP(launch_morton_order(v.keys, v.n_nodes, code, code_sorted, ids, c->order, rank, tmpm, &bm, s));
+    SAL_HIP(launch_edge_directed(occ_sorted, head, pos, n_occ, n_edges, start, rank, dkeys, cnt + 1, s));
     size_t b3 = 0;
     SAL_HIP(sort_keys_u64(dkeys, dsorted, n2, 32 + nb, nullptr, &b3, s));
     char *tmp3 = nullptr;
@@ -103,7 +116,7 @@ sal_status build_graph(const ConformView &v, SmoothCache *c, hipStream_t s) {
         (st = dev_alloc(&c->cls, v.n_nodes)) != SAL_OK)
         return st;
     SAL_HIP(launch_csr(dsorted, n2, v.n_nodes, c->rowptr, c->cols, s));
-    SAL_HIP(launch_node_class(c->rowptr, c->cols, v.keys, v.n_nodes, v.g, c->cls, s));
+    SAL_HIP(launch_node_class(c->rowptr, c->cols, v.keys, c->order, v.n_nodes, v.g, c->cls, s));
     // node lists of the two phases, in node order
     int64_t *blocks = nullptr, *totals = nullptr;
     if ((st = t.get(&blocks, compact_blocks(v.n_nodes) + 1)) != SAL_OK || (st = t.get(&totals, 2)) != SAL_OK)
@@ -120,10 +133,20 @@ sal_status build_graph(const ConformView &v, SmoothCache *c, hipStream_t s) {
     c->n_surface_edges = (int64_t)hcnt[1];
     c->n_nodes = v.n_nodes;
     c->n_edges = n_edges;
-    c->partials_cap = smooth_blocks(std::max(c->n_list[0], c->n_list[1]));
+    c->partials_cap = taubin_blocks(std::max(c->n_list[0], c->n_list[1]));
     if ((st = dev_alloc(&c->partials, c->partials_cap)) != SAL_OK || (st = dev_alloc(&c->sum, 1)) != SAL_OK ||
         (st = dev_alloc(&c->pos[0], v.n_nodes)) != SAL_OK || (st = dev_alloc(&c->pos[1], v.n_nodes)) != SAL_OK)
         return st;
+    if (n2 >= (int64_t(1) << 32)) return set_error(SAL_ERR_CAPACITY, "smoothing: 2^32 row entries or more");
+    for (int ph = 0; ph < 2; ++ph) {
+        if ((st = dev_alloc(&c->seg[ph], c->n_list[ph])) != SAL_OK) return st;
+        SAL_HIP(launch_row_segments(c->rowptr, c->list[ph], c->n_list[ph], c->seg[ph], s));
+        double e = 0.0;
+        SAL_HIP(launch_row_entries(c->rowptr, c->list[ph], c->n_list[ph], c->partials, c->sum, s));
+        SAL_HIP(hipMemcpyAsync(&e, c->sum, sizeof(e), hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipStreamSynchronize(s));
+        c->n_entries[ph] = (int64_t)e;
+    }
     return SAL_OK;
 }
 
@@ -150,10 +173,10 @@ sal_status run_phase(SmoothCache *c, int ph, double lam, double mu, double xi, i
     if ((st = read_sum(c, &norm0, s)) != SAL_OK) return st;
     norm0 = std::sqrt(norm0);
     for (int k = 0; k < max_iter; ++k) {
-        SAL_HIP(launch_taubin_half(c->pos[0], c->pos[1], c->rowptr, c->cols, c->list[ph], n, lam,
+        SAL_HIP(launch_taubin_half(c->pos[0], c->pos[1], c->seg[ph], c->cols, c->list[ph], n, lam,
                                    ph == 0, c->partials, c->sum, s));
         SAL_HIP(hipMemcpyAsync(&step, c->sum, sizeof(double), hipMemcpyDeviceToHost, s));
-        SAL_HIP(launch_taubin_half(c->pos[1], c->pos[0], c->rowptr, c->cols, c->list[ph], n, -mu,
+        SAL_HIP(launch_taubin_half(c->pos[1], c->pos[0], c->seg[ph], c->cols, c->list[ph], n, -mu,
                                    ph == 0, c->partials, c->sum, s));
         SAL_HIP(hipStreamSynchronize(s));
         *iters = k + 1;
@@ -215,7 +238,7 @@ sal_status sal_tet_mesh_smooth(sal_context *ctx, sal_tet_mesh *m, const sal_smoo
             *v.cache = c;
         }
         SmoothCache *c = *v.cache;
-        SAL_HIP(launch_pack_pos(v.xyz, v.n_nodes, c->pos[0], c->pos[1], s));
+        SAL_HIP(launch_pack_pos(v.xyz, c->order, v.n_nodes, c->pos[0], c->pos[1], s));
         int32_t it[2] = {0, 0};
         double ratio[2] = {0.0, 0.0};
         float ms[2] = {0.0f, 0.0f};
@@ -229,7 +252,7 @@ sal_status sal_tet_mesh_smooth(sal_context *ctx, sal_tet_mesh *m, const sal_smoo
             SAL_HIP(hipEventSynchronize(ctx->ev[3]));
             ms[ph] = elapsed_ms(ctx->ev[2], ctx->ev[3]);
         }
-        SAL_HIP(launch_unpack_pos(c->pos[0], v.n_nodes, v.xyz, s));
+        SAL_HIP(launch_unpack_pos(c->pos[0], c->order, v.n_nodes, v.xyz, s));
         SAL_HIP(hipStreamSynchronize(s));
         if (info) {
             std::memset(info, 0, sizeof(*info));
@@ -244,6 +267,8 @@ sal_status sal_tet_mesh_smooth(sal_context *ctx, sal_tet_mesh *m, const sal_smoo
             info->ms_build = ms_build;
             info->ms_surface = ms[0];
             info->ms_volume = ms[1];
+            info->n_entries_surface = c->n_entries[0];
+            info->n_entries_volume = c->n_entries[1];
         }
         return SAL_OK;
     } catch (...) {

@@ -36,6 +36,34 @@ __global__ void k_edge_occurrences(const int32_t *__restrict__ ids, const int32_
     keys[jj] = (lo << 36) | (hi << 8) | (uint64_t)(uint8_t)(lab + 1);
 }
 
+// Morton code of a node (its three 21-bit finest-grid coordinates
+// interleaved): numbering the nodes in this order keeps the neighbours of a
+// node close in memory in every direction.
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ void k_morton_codes(const int64_t *__restrict__ keys, int64_t n, uint64_t *__restrict__ code,
+                               int32_t *__restrict__ ids) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = (uint64_t)keys[i];
+    code[i] = (spread3(k >> 42) << 2) | (spread3(k >> 21) << 1) | spread3(k);
+    ids[i] = (int32_t)i;
+}
+
+__global__ void k_rank_of(const int32_t *__restrict__ order, int64_t n, int32_t *__restrict__ rank) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    rank[order[r]] = (int32_t)r;
+}
+
 __global__ void k_edge_heads(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ head) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -49,12 +77,12 @@ __global__ void k_edge_starts(const int32_t *__restrict__ head, const int64_t *_
     start[pos[i]] = i;
 }
 
-// Both directions of edge e: (row << 32) | (col << 1) | interface, where the
-// edge is an interface edge when its occurrences carry different labels
-// (sorted, so the first and the last differ).
+// Both directions of edge e in Morton ranks: (row << 32) | (col << 1) |
+// interface, where the edge is an interface edge when its occurrences carry
+// different labels (sorted, so the first and the last differ).
 __global__ void k_edge_emit(const uint64_t *__restrict__ keys, const int64_t *__restrict__ start,
-                            int64_t n, int64_t n_edges, uint64_t *__restrict__ dkeys,
-                            unsigned long long *__restrict__ n_surf) {
+                            int64_t n, int64_t n_edges, const int32_t *__restrict__ rank,
+                            uint64_t *__restrict__ dkeys, unsigned long long *__restrict__ n_surf) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t surf = 0;
     if (e < n_edges) {
@@ -62,12 +90,18 @@ __global__ void k_edge_emit(const uint64_t *__restrict__ keys, const int64_t *__
         const int64_t last = (e + 1 < n_edges ? start[e + 1] : n) - 1;
         const uint64_t k = keys[s];
         surf = (k & 0xffu) != (keys[last] & 0xffu) ? 1u : 0u;
-        const uint64_t a = k >> 36, b = (k >> 8) & ((1ull << 28) - 1);
+        const uint64_t a = (uint64_t)rank[k >> 36], b = (uint64_t)rank[(k >> 8) & ((1ull << 28) - 1)];
         dkeys[2 * e] = (a << 32) | (b << 1) | surf;
         dkeys[2 * e + 1] = (b << 32) | (a << 1) | surf;
     }
+    // one counter update per block
+    __shared__ unsigned int block_count;
+    if (threadIdx.x == 0) block_count = 0;
+    __syncthreads();
     const unsigned long long m = __ballot(surf != 0);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_surf, (unsigned long long)__popcll(m));
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&block_count, (unsigned int)__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0 && block_count) atomicAdd(n_surf, (unsigned long long)block_count);
 }
 
 // Row pointers from the sorted directed keys (rows without an entry get an
@@ -85,14 +119,14 @@ __global__ void k_csr(const uint64_t *__restrict__ dkeys, int64_t n2, int64_t n_
         for (int64_t q = r + 1; q <= n_nodes; ++q) rowptr[q] = n2;
 }
 
-// 0: on a face of the lattice box (never moves); 1: on an interface
-// (surface phase); 2: any other node (volume phase).
+// Per Morton rank: 0 on a face of the lattice box (never moves); 1 on an
+// interface (surface phase); 2 any other node (volume phase).
 __global__ void k_node_class(const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ cols,
-                             const int64_t *__restrict__ keys, int64_t n, LatticeGeom g,
-                             uint8_t *__restrict__ cls) {
+                             const int64_t *__restrict__ keys, const int32_t *__restrict__ order,
+                             int64_t n, LatticeGeom g, uint8_t *__restrict__ cls) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint64_t k = (uint64_t)keys[i];
+    const uint64_t k = (uint64_t)keys[order[i]];
     const int64_t f[3] = {(int64_t)((k >> 42) & 0x1fffffu), (int64_t)((k >> 21) & 0x1fffffu),
                           (int64_t)(k & 0x1fffffu)};
     bool box = false;
@@ -102,19 +136,23 @@ __global__ void k_node_class(const int64_t *__restrict__ rowptr, const uint32_t 
     cls[i] = box ? 0 : (surf ? 1 : 2);
 }
 
-__global__ void k_pack_pos(const float *__restrict__ xyz, int64_t n, float4 *__restrict__ a,
-                           float4 *__restrict__ b) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Positions in Morton rank order (rank r holds node order[r]).
+__global__ void k_pack_pos(const float *__restrict__ xyz, const int32_t *__restrict__ order, int64_t n,
+                           float4 *__restrict__ a, float4 *__restrict__ b) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t i = order[r];
     const float4 p = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], 0.0f);
-    a[i] = p;
-    b[i] = p;
+    a[r] = p;
+    b[r] = p;
 }
 
-__global__ void k_unpack_pos(const float4 *__restrict__ p, int64_t n, float *__restrict__ xyz) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float4 q = p[i];
+__global__ void k_unpack_pos(const float4 *__restrict__ p, const int32_t *__restrict__ order, int64_t n,
+                             float *__restrict__ xyz) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t i = order[r];
+    const float4 q = p[r];
     xyz[3 * i] = q.x;
     xyz[3 * i + 1] = q.y;
     xyz[3 * i + 2] = q.z;
@@ -144,6 +182,18 @@ __global__ __launch_bounds__(kSmoothThreads) void k_norm_sq(const float4 *__rest
     block_sum(v, partials);
 }
 
+__global__ __launch_bounds__(kSmoothThreads) void k_row_entries(const int64_t *__restrict__ rowptr,
+                                                               const int32_t *__restrict__ list,
+                                                               int64_t n, double *__restrict__ partials) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (t < n) {
+        const int32_t i = list[t];
+        v = (double)(rowptr[i + 1] - rowptr[i]);
+    }
+    block_sum(v, partials);
+}
+
 // One block: thread j sums partials j, j + 1024, ... in order, then a tree.
 __global__ __launch_bounds__(1024) void k_sum_partials(const double *__restrict__ partials, int64_t nb,
                                                        double *__restrict__ out) {
@@ -159,28 +209,82 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double *__restrict_
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// Row segment of each listed node: (first entry << 32) | length, so a half
+// step reads it with the node id instead of after it.
+__global__ void k_row_segments(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ list,
+                               int64_t n, uint64_t *__restrict__ seg) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t i = list[t];
+    const int64_t b = rowptr[i];
+    seg[t] = ((uint64_t)b << 32) | (uint64_t)(rowptr[i + 1] - b);
+}
+
+// kTaubinGroup lanes per node, each taking every kTaubinGroup-th entry of
+// the row.  The first kTaubinUnroll entries of a lane are loaded together
+// (all column loads, then all position gathers), so a node costs two
+// dependent memory round trips, not two per neighbour; longer rows finish
+// in a plain loop.  The group's double sums are combined by a fixed
+// butterfly and its first lane writes the node.
 __global__ __launch_bounds__(kSmoothThreads) void k_taubin_half(
-    const float4 *__restrict__ in, float4 *__restrict__ out, const int64_t *__restrict__ rowptr,
+    const float4 *__restrict__ in, float4 *__restrict__ out, const uint64_t *__restrict__ seg,
     const uint32_t *__restrict__ cols, const int32_t *__restrict__ list, int64_t n, double coef,
     int surface_only, double *__restrict__ partials) {
 #pragma clang fp contract(off)
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double d2 = 0.0;
+    constexpr int G = kTaubinGroup, U = kTaubinUnroll;
+    const int lane = (int)(threadIdx.x & (G - 1));
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    int cnt = 0;
+    int32_t i = 0;
     if (t < n) {
-        const int32_t i = list[t];
-        const float4 xi = in[i];
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        int cnt = 0;
+        i = list[t];
+        const uint64_t sg = seg[t];
+        const int64_t beg = (int64_t)(sg >> 32), len = (int64_t)(sg & 0xffffffffu);
         const uint32_t need = surface_only ? kSurfBit : 0u;
-        for (int64_t q = rowptr[i], end = rowptr[i + 1]; q < end; ++q) {
-            const uint32_t c = cols[q];
-            if ((c & need) != need) continue;
-            const float4 p = in[c & ~kSurfBit];
-            sx += (double)p.x;
-            sy += (double)p.y;
-            sz += (double)p.z;
+        uint32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = lane + (int64_t)u * G;
+            c[u] = q < len ? cols[beg + q] : 0u;
+        }
+        float4 p[U];
+        unsigned use = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = lane + (int64_t)u * G;
+            const bool ok = q < len && (c[u] & need) == need;
+            use |= ok ? 1u << u : 0u;
+            p[u] = ok ? in[c[u] & ~kSurfBit] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (use >> u & 1u) {
+                sx += (double)p[u].x;
+                sy += (double)p[u].y;
+                sz += (double)p[u].z;
+                ++cnt;
+            }
+        }
+        for (int64_t q = lane + (int64_t)U * G; q < len; q += G) {
+            const uint32_t cq = cols[beg + q];
+            if ((cq & need) != need) continue;
+            const float4 pq = in[cq & ~kSurfBit];
+            sx += (double)pq.x;
+            sy += (double)pq.y;
+            sz += (double)pq.z;
             ++cnt;
         }
+    }
+    for (int off = G / 2; off > 0; off >>= 1) {
+        sx += __shfl_xor(sx, off, G);
+        sy += __shfl_xor(sy, off, G);
+        sz += __shfl_xor(sz, off, G);
+        cnt += __shfl_xor(cnt, off, G);
+    }
+    double d2 = 0.0;
+    if (t < n && lane == 0) {
+        const float4 xi = in[i];
         // mean over the node and its neighbours, then the step toward it
         const double inv = (double)(cnt + 1);
         const double mx = (sx + (double)xi.x) / inv, my = (sy + (double)xi.y) / inv,
@@ -200,6 +304,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_taubin_half(
 }  // namespace
 
 int64_t smooth_blocks(int64_t n) { return (n + kSmoothThreads - 1) / kSmoothThreads; }
+int64_t taubin_blocks(int64_t n) { return (n * kTaubinGroup + kSmoothThreads - 1) / kSmoothThreads; }
 
 hipError_t launch_edge_occurrences(const int32_t *ids, const int32_t *labels, int64_t n_tets,
                                    uint64_t *keys, unsigned long long *bad_labels, hipStream_t s) {
@@ -226,11 +331,12 @@ hipError_t exclusive_sum_head(const int32_t *head, int64_t *pos, int64_t n, void
 }
 
 hipError_t launch_edge_directed(const uint64_t *keys, const int32_t *head, const int64_t *pos,
-                                int64_t n, int64_t n_edges, int64_t *start, uint64_t *dkeys,
-                                unsigned long long *n_surf, hipStream_t s) {
+                                int64_t n, int64_t n_edges, int64_t *start, const int32_t *rank,
+                                uint64_t *dkeys, unsigned long long *n_surf, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_edge_starts<<<grid_of(n), kSmoothThreads, 0, s>>>(head, pos, n, start);
-    k_edge_emit<<<grid_of(n_edges), kSmoothThreads, 0, s>>>(keys, start, n, n_edges, dkeys, n_surf);
+    k_edge_emit<<<grid_of(n_edges), kSmoothThreads, 0, s>>>(keys, start, n, n_edges, rank, dkeys,
+                                                           n_surf);
     return hipGetLastError();
 }
 
@@ -241,22 +347,40 @@ hipError_t launch_csr(const uint64_t *dkeys, int64_t n2, int64_t n_nodes, int64_
     return hipGetLastError();
 }
 
+hipError_t launch_morton_order(const int64_t *keys, int64_t n, uint64_t *code, uint64_t *code_sorted,
+                               int32_t *ids, int32_t *order, int32_t *rank, void *tmp,
+                               size_t *tmp_bytes, hipStream_t s) {
+    if (!tmp)
+        return hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, code, code_sorted, ids, order, (int)n,
+                                                  0, 63, s);
+    if (n <= 0) return hipSuccess;
+    k_morton_codes<<<grid_of(n), kSmoothThreads, 0, s>>>(keys, n, code, ids);
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, code, code_sorted, ids, order,
+                                                      (int)n, 0, 63, s);
+    if (e != hipSuccess) return e;
+    k_rank_of<<<grid_of(n), kSmoothThreads, 0, s>>>(order, n, rank);
+    return hipGetLastError();
+}
+
 hipError_t launch_node_class(const int64_t *rowptr, const uint32_t *cols, const int64_t *keys,
-                             int64_t n_nodes, const LatticeGeom &g, uint8_t *cls, hipStream_t s) {
+                             const int32_t *order, int64_t n_nodes, const LatticeGeom &g, uint8_t *cls,
+                             hipStream_t s) {
     if (n_nodes <= 0) return hipSuccess;
-    k_node_class<<<grid_of(n_nodes), kSmoothThreads, 0, s>>>(rowptr, cols, keys, n_nodes, g, cls);
+    k_node_class<<<grid_of(n_nodes), kSmoothThreads, 0, s>>>(rowptr, cols, keys, order, n_nodes, g, cls);
     return hipGetLastError();
 }
 
-hipError_t launch_pack_pos(const float *xyz, int64_t n, float4 *a, float4 *b, hipStream_t s) {
+hipError_t launch_pack_pos(const float *xyz, const int32_t *order, int64_t n, float4 *a, float4 *b,
+                           hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_pack_pos<<<grid_of(n), kSmoothThreads, 0, s>>>(xyz, n, a, b);
+    k_pack_pos<<<grid_of(n), kSmoothThreads, 0, s>>>(xyz, order, n, a, b);
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_pos(const float4 *p, int64_t n, float *xyz, hipStream_t s) {
+hipError_t launch_unpack_pos(const float4 *p, const int32_t *order, int64_t n, float *xyz,
+                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_unpack_pos<<<grid_of(n), kSmoothThreads, 0, s>>>(p, n, xyz);
+    k_unpack_pos<<<grid_of(n), kSmoothThreads, 0, s>>>(p, order, n, xyz);
     return hipGetLastError();
 }
 
@@ -268,12 +392,27 @@ hipError_t launch_norm_sq(const float4 *p, const int32_t *list, int64_t n, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_taubin_half(const float4 *in, float4 *out, const int64_t *rowptr,
+hipError_t launch_row_entries(const int64_t *rowptr, const int32_t *list, int64_t n, double *partials,
+                              double *sum, hipStream_t s) {
+    const int64_t nb = smooth_blocks(n);
+    if (nb > 0) k_row_entries<<<(unsigned)nb, kSmoothThreads, 0, s>>>(rowptr, list, n, partials);
+    k_sum_partials<<<1, 1024, 0, s>>>(partials, nb, sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_segments(const int64_t *rowptr, const int32_t *list, int64_t n, uint64_t *seg,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_row_segments<<<grid_of(n), kSmoothThreads, 0, s>>>(rowptr, list, n, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_taubin_half(const float4 *in, float4 *out, const uint64_t *seg,
                               const uint32_t *cols, const int32_t *list, int64_t n, double coef,
                               int surface_only, double *partials, double *sum, hipStream_t s) {
-    const int64_t nb = smooth_blocks(n);
+    const int64_t nb = taubin_blocks(n);
     if (nb > 0)
-        k_taubin_half<<<(unsigned)nb, kSmoothThreads, 0, s>>>(in, out, rowptr, cols, list, n, coef,
+        k_taubin_half<<<(unsigned)nb, kSmoothThreads, 0, s>>>(in, out, seg, cols, list, n, coef,
                                                               surface_only, partials);
     k_sum_partials<<<1, 1024, 0, s>>>(partials, nb, sum);
     return hipGetLastError();
