@@ -23,30 +23,45 @@ Brute force over every triangle, float64, in the order written above.
 import numpy as np
 
 
+def _dot(a, b):
+    return (a[..., 0] * b[..., 0] + a[..., 1] * b[..., 1]) + a[..., 2] * b[..., 2]
+
+
+def _cross(a, b):
+    return np.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
+                     a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2],
+                     a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]], -1)
+
+
 def segment_hits(p, q, tris):
     """Parameters t in [0, 1] where segment p -> q meets each triangle
-    (tris [T, 3, 3]); NaN where it does not (parallel included)."""
+    (tris [T, 3, 3]); NaN where it does not (parallel included).  Products
+    and sums are written out one by one (no fused operations)."""
     p = np.asarray(p, dtype=np.float64)
     d = np.asarray(q, dtype=np.float64) - p
     v0, v1, v2 = tris[:, 0], tris[:, 1], tris[:, 2]
     e1 = v1 - v0
     e2 = v2 - v0
-    h = np.cross(d, e2)
-    a = np.einsum("ij,ij->i", e1, h)
+    h = _cross(d, e2)
+    a = _dot(e1, h)
     with np.errstate(divide="ignore", invalid="ignore"):
         f = 1.0 / a
         s = p - v0
-        u = f * np.einsum("ij,ij->i", s, h)
-        qv = np.cross(s, e1)
-        v = f * (qv @ d)
-        t = f * np.einsum("ij,ij->i", e2, qv)
+        u = f * _dot(s, h)
+        qv = _cross(s, e1)
+        v = f * _dot(d, qv)
+        t = f * _dot(e2, qv)
         ok = (a != 0) & (u >= 0) & (u <= 1) & (v >= 0) & (u + v <= 1) & (t >= 0) & (t <= 1)
     return np.where(ok, t, np.nan)
 
 
 def triangles(surfaces):
-    """All triangles of the set as float64 [T, 3, 3]."""
-    return np.concatenate([s.v.astype(np.float64)[s.f] for s in surfaces])
+    """All triangles of the set as float64 [T, 3, 3], each with its vertices
+    in lexicographic (x, y, z) order so that the crossing arithmetic does not
+    depend on how a triangle was listed."""
+    tri = np.concatenate([s.v.astype(np.float64)[s.f] for s in surfaces])
+    order = np.lexsort((tri[:, :, 2], tri[:, :, 1], tri[:, :, 0]), axis=-1)
+    return np.take_along_axis(tri, order[:, :, None], axis=1)
 
 
 def inflate(xyz, edges, movable, node_keys, tris, zeta=0.05):
@@ -68,7 +83,7 @@ def inflate(xyz, edges, movable, node_keys, tris, zeta=0.05):
             t = segment_hits(xyz[i], xyz[j], tris)
             if np.all(np.isnan(t)):
                 continue
-            length = np.sqrt(np.sum((xyz[j] - xyz[i]) ** 2))
+            length = np.sqrt(_dot(xyz[j] - xyz[i], xyz[j] - xyz[i]))
             d = np.nanmin(t) * length
             cand = (d, int(node_keys[j]), j, length)
             if best is None or cand[:2] < best[:2]:
