@@ -361,6 +361,34 @@ typedef struct sal_smooth_info {
 sal_status sal_tet_mesh_smooth(sal_context *ctx, sal_tet_mesh *mesh, const sal_smooth_params *params,
                                sal_smooth_info *info);
 
+/* -------------------------------------------------------------- inflation */
+typedef struct sal_inflate_info {
+    int64_t n_candidates;     /* interface nodes off the lattice box */
+    int64_t n_moved;          /* of those, nodes with an edge crossing a triangle */
+    int64_t n_edges_tested;   /* their incident edges (directed) */
+    int64_t n_triangle_tests; /* segment-triangle tests made */
+    int64_t n_triangles;      /* triangles of the surface set */
+    int64_t n_bin_items;      /* (bin, triangle) entries of the lattice binning */
+    float ms_prepare;         /* triangles, binning, edge graph if not built yet */
+    float ms_inflate;         /* the move */
+} sal_inflate_info;
+
+/* Section 2.2.2: moves every interface node of the conforming mesh (an edge
+ * of the node joins tetrahedra of two or more labels; nodes on the lattice
+ * box excepted) toward the surfaces.  Each incident edge x_i -> x_j is
+ * tested against the triangles of `set` (segment-triangle crossing, bounds
+ * included, in double); over the edges, the crossing nearest to x_i along its
+ * edge, at distance d, wins (equal distances: the neighbour with the smaller
+ * node key), and x_i <- x_i + zeta d (x_j - x_i) / |x_j - x_i|.  Nodes whose
+ * edges cross no triangle stay; all moves read the positions from before the
+ * call.  Positions are kept in float32.  The surface set is the one the mesh
+ * was labeled with, or any other on the same device.
+ *   zeta  in [0, 1) (section 3 uses 0.05);  info  NULL, or filled
+ * Errors: SAL_ERR_INVALID_ARG before sal_tet_mesh_conform or for zeta
+ * outside [0, 1); SAL_ERR_CAPACITY as for sal_tet_mesh_smooth. */
+sal_status sal_tet_mesh_inflate(sal_context *ctx, sal_tet_mesh *mesh, const sal_surface_set *set,
+                                double zeta, sal_inflate_info *info);
+
 /* ------------------------------------------------------------ batched form
  * Many independent labeling problems in one persistent launch: the work is
  * cut into (instance, point block, surface, triangle range) items ordered by

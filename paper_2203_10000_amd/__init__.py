@@ -107,6 +107,16 @@ class SmoothInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class InflateInfo(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int64), ("n_moved", ctypes.c_int64),
+                ("n_edges_tested", ctypes.c_int64), ("n_triangle_tests", ctypes.c_int64),
+                ("n_triangles", ctypes.c_int64), ("n_bin_items", ctypes.c_int64),
+                ("ms_prepare", ctypes.c_float), ("ms_inflate", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("surfaces", ctypes.c_void_p), ("n_points", ctypes.c_int64),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
@@ -146,6 +156,8 @@ _SIGNATURES = [
     ("sal_smooth_params_default", None, [ctypes.POINTER(SmoothParams)]),
     ("sal_tet_mesh_smooth", ctypes.c_int,
      [_P, _P, ctypes.POINTER(SmoothParams), ctypes.POINTER(SmoothInfo)]),
+    ("sal_tet_mesh_inflate", ctypes.c_int,
+     [_P, _P, _P, ctypes.c_double, ctypes.POINTER(InflateInfo)]),
     ("sal_label_batch", ctypes.c_int,
      [_P, ctypes.POINTER(Instance), ctypes.c_int32, ctypes.POINTER(LabelOptions),
       ctypes.POINTER(LabelStats)]),
@@ -381,6 +393,13 @@ class TetMesh:
         info = SmoothInfo()
         _check(lib().sal_tet_mesh_smooth(self.ctx.handle, self.handle, ctypes.byref(p),
                                          ctypes.byref(info)))
+        return info.as_dict()
+
+    def inflate(self, sset, zeta=0.05):
+        """sal_tet_mesh_inflate against the surfaces of `sset`; returns the info."""
+        info = InflateInfo()
+        _check(lib().sal_tet_mesh_inflate(self.ctx.handle, self.handle, sset.handle, float(zeta),
+                                          ctypes.byref(info)))
         return info.as_dict()
 
     def close(self):

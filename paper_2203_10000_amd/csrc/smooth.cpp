@@ -186,6 +186,22 @@ sal_status run_phase(SmoothCache *c, int ph, double lam, double mu, double xi, i
     return SAL_OK;
 }
 
+}  // namespace
+
+sal_status ensure_smooth_graph(const ConformView &v, hipStream_t s) {
+    if (*v.cache) return SAL_OK;
+    auto *c = new SmoothCache();
+    const sal_status st = build_graph(v, c, s);
+    if (st != SAL_OK) {
+        smooth_cache_free(c);
+        return st;
+    }
+    *v.cache = c;
+    return SAL_OK;
+}
+
+namespace {
+
 float elapsed_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0.0f;
     return hipEventElapsedTime(&ms, a, b) == hipSuccess ? ms : 0.0f;
@@ -225,17 +241,11 @@ sal_status sal_tet_mesh_smooth(sal_context *ctx, sal_tet_mesh *m, const sal_smoo
         sal_status st;
         float ms_build = 0.0f;
         if (!*v.cache) {
-            auto *c = new SmoothCache();
             SAL_HIP(hipEventRecord(ctx->ev[0], s));
-            st = build_graph(v, c, s);
-            if (st != SAL_OK) {
-                smooth_cache_free(c);
-                return st;
-            }
+            if ((st = ensure_smooth_graph(v, s)) != SAL_OK) return st;
             SAL_HIP(hipEventRecord(ctx->ev[1], s));
             SAL_HIP(hipEventSynchronize(ctx->ev[1]));
             ms_build = elapsed_ms(ctx->ev[0], ctx->ev[1]);
-            *v.cache = c;
         }
         SmoothCache *c = *v.cache;
         SAL_HIP(launch_pack_pos(v.xyz, c->order, v.n_nodes, c->pos[0], c->pos[1], s));
