@@ -46,6 +46,8 @@ def parse():
                     help="c3: then build the conforming transition mesh and check it")
     ap.add_argument("--smooth", action="store_true",
                     help="c3: conforming mesh, then Taubin smoothing (implies --conform)")
+    ap.add_argument("--inflate", action="store_true",
+                    help="c3: conforming mesh, smoothing, then inflation (implies --smooth)")
     ap.add_argument("--smooth-iters", type=int, default=10,
                     help="iterations per phase of the fixed-count smoothing run")
     ap.add_argument("--c5-lattice-fraction", type=float, default=0.125,
@@ -266,6 +268,18 @@ def _smooth_c3(mesh, iters):
     return out
 
 
+def _inflate_c3(mesh, ss):
+    """Inflation of the smoothed c3 mesh with zeta = 0.05 (timed by the
+    library's events: triangle binning, then the move)."""
+    progress("c3: inflation")
+    first = mesh.inflate(ss, 0.05)
+    again = mesh.inflate(ss, 0.05)
+    ms = again["ms_inflate"]
+    return {"first": first, "second": again,
+            "triangle_tests_per_s": again["n_triangle_tests"] / (ms * 1e-3),
+            "edges_per_s": again["n_edges_tested"] / (ms * 1e-3)}
+
+
 def run_c3(args):
     """c3: 20 compartments (4 x 81,920 + 16 x 5,120 triangles), 1 mm lattice
     (48M centroids), two refine-and-relabel rounds in FP32 + recheck."""
@@ -300,10 +314,12 @@ def run_c3(args):
                                             near)
     else:
         mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, near)
-    out_conform = _conform_c3(mesh, lat, rng) if (args.conform or args.smooth) else None
-    out_smooth = _smooth_c3(mesh, args.smooth_iters) if args.smooth else None
+    post = args.conform or args.smooth or args.inflate
+    out_conform = _conform_c3(mesh, lat, rng) if post else None
+    out_smooth = _smooth_c3(mesh, args.smooth_iters) if (args.smooth or args.inflate) else None
+    out_inflate = _inflate_c3(mesh, ss) if args.inflate else None
     return {"workload": "c3", "rule": args.rule, "triangles": cfg.n_tri, "rounds": st,
-            "conform": out_conform, "smooth": out_smooth,
+            "conform": out_conform, "smooth": out_smooth, "inflate": out_inflate,
             "leaves": n_leaves,
             "max_level": lv, "pairs": pairs, "wall_s": wall,
             "g_pairs_per_s": pairs / wall / 1e9,

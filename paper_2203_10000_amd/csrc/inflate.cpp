@@ -1,5 +1,5 @@
 // Inflation of the compartment boundaries (paper section 2.2.2): host side.
-// Per call the surface set's strips are unrolled into double triangles and
+// Per call the surface set's strips are unrolled into float32 triangles and
 // binned on the level-0 lattice; the interface nodes of the conforming mesh
 // then move in one launch that reads the positions from before the call.
 #include <algorithm>
@@ -64,7 +64,7 @@ sal_status sal_tet_mesh_inflate(sal_context *ctx, sal_tet_mesh *m, const sal_sur
             n_tri += set->host_strip_tris[k];
         }
         int64_t *tri_base = nullptr;
-        double *tri = nullptr;
+        float *tri = nullptr;
         if ((st = b.get(&tri_base, (int64_t)base.size())) != SAL_OK || (st = b.get(&tri, 9 * n_tri)) != SAL_OK)
             return st;
         SAL_HIP(hipMemcpyAsync(tri_base, base.data(), base.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));

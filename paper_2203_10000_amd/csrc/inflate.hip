@@ -28,10 +28,11 @@ __device__ __forceinline__ bool lex_less(const double *a, const double *b) {
 
 // Triangles of strip s: (v_k, v_k+1, v_k+2) with v_0, v_1 in the head record
 // and v_k+2 the vertex of the k-th record after it; stored with sorted
-// vertices.
+// vertices, in float32 (the surface vertices are float32 values, so this
+// loses nothing and halves the bytes each test reads).
 __global__ void k_strip_triangles(const Rec64 *__restrict__ rec, const int64_t *__restrict__ strip_off,
                                   const int64_t *__restrict__ tri_base, int64_t n_strips,
-                                  double *__restrict__ tri) {
+                                  float *__restrict__ tri) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_strips) return;
     const int64_t h = strip_off[s];
@@ -49,9 +50,9 @@ __global__ void k_strip_triangles(const Rec64 *__restrict__ rec, const int64_t *
         if (lex_less(p[1], p[0])) { const double *x = p[0]; p[0] = p[1]; p[1] = x; }
         if (lex_less(p[2], p[1])) { const double *x = p[1]; p[1] = p[2]; p[2] = x; }
         if (lex_less(p[1], p[0])) { const double *x = p[0]; p[0] = p[1]; p[1] = x; }
-        double *o = tri + 9 * (tri_base[s] + k);
+        float *o = tri + 9 * (tri_base[s] + k);
         for (int v = 0; v < 3; ++v)
-            for (int c = 0; c < 3; ++c) o[3 * v + c] = p[v][c];
+            for (int c = 0; c < 3; ++c) o[3 * v + c] = (float)p[v][c];
         for (int c = 0; c < 3; ++c) {
             w[0][c] = w[1][c];
             w[1][c] = w[2][c];
@@ -82,16 +83,16 @@ __device__ __forceinline__ int64_t bin_index(int x, int y, int z, const LatticeG
 }
 
 // pass 0: count triangles per bin; pass 1: place them (cursor per bin).
-__global__ void k_bin_triangles(const double *__restrict__ tri, int64_t n_tri, LatticeGeom g, int pass,
+__global__ void k_bin_triangles(const float *__restrict__ tri, int64_t n_tri, LatticeGeom g, int pass,
                                 int32_t *__restrict__ count, const int64_t *__restrict__ start,
                                 int32_t *__restrict__ items) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tri) return;
-    const double *v = tri + 9 * t;
+    const float *v = tri + 9 * t;
     double lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
-        lo[a] = fmin(fmin(v[a], v[3 + a]), v[6 + a]);
-        hi[a] = fmax(fmax(v[a], v[3 + a]), v[6 + a]);
+        lo[a] = fmin(fmin((double)v[a], (double)v[3 + a]), (double)v[6 + a]);
+        hi[a] = fmax(fmax((double)v[a], (double)v[3 + a]), (double)v[6 + a]);
     }
     const BinBox b = box_bins(lo, hi, g);
     for (int z = b.lo[2]; z <= b.hi[2]; ++z)
@@ -103,9 +104,11 @@ __global__ void k_bin_triangles(const double *__restrict__ tri, int64_t n_tri, L
             }
 }
 
-// Segment p -> p + d against triangle v (9 doubles): t in [0, 1], or -1.
-__device__ __forceinline__ double crossing(const double p[3], const double d[3], const double *v) {
+// Segment p -> p + d against triangle tv (9 floats): t in [0, 1], or -1.
+__device__ __forceinline__ double crossing(const double p[3], const double d[3], const float *tv) {
 #pragma clang fp contract(off)
+    double v[9];
+    for (int k = 0; k < 9; ++k) v[k] = (double)tv[k];
     const double e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
     const double e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
     const double h[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
@@ -130,7 +133,7 @@ __device__ __forceinline__ double crossing(const double p[3], const double d[3],
 __global__ __launch_bounds__(kSmoothThreads) void k_inflate(
     const float4 *__restrict__ in, float4 *__restrict__ out, const uint64_t *__restrict__ seg,
     const uint32_t *__restrict__ cols, const int32_t *__restrict__ list, int64_t n,
-    const int32_t *__restrict__ order, const int64_t *__restrict__ keys, const double *__restrict__ tri,
+    const int32_t *__restrict__ order, const int64_t *__restrict__ keys, const float *__restrict__ tri,
     const int64_t *__restrict__ bin_start, const int32_t *__restrict__ bin_items, LatticeGeom g,
     double zeta, double *__restrict__ partials) {
 #pragma clang fp contract(off)
@@ -257,13 +260,13 @@ __global__ __launch_bounds__(1024) void k_sum_pairs(const double *__restrict__ p
 int64_t inflate_blocks(int64_t n) { return (n * kInflateGroup + kSmoothThreads - 1) / kSmoothThreads; }
 
 hipError_t launch_strip_triangles(const Rec64 *rec, const int64_t *strip_off, const int64_t *tri_base,
-                                  int64_t n_strips, double *tri, hipStream_t s) {
+                                  int64_t n_strips, float *tri, hipStream_t s) {
     if (n_strips <= 0) return hipSuccess;
     k_strip_triangles<<<grid_of(n_strips), kSmoothThreads, 0, s>>>(rec, strip_off, tri_base, n_strips, tri);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_triangles(const double *tri, int64_t n_tri, const LatticeGeom &g, int pass,
+hipError_t launch_bin_triangles(const float *tri, int64_t n_tri, const LatticeGeom &g, int pass,
                                 int32_t *count, const int64_t *start, int32_t *items, hipStream_t s) {
     if (n_tri <= 0) return hipSuccess;
     k_bin_triangles<<<grid_of(n_tri), kSmoothThreads, 0, s>>>(tri, n_tri, g, pass, count, start, items);
@@ -277,7 +280,7 @@ hipError_t exclusive_sum_bins(const int32_t *count, int64_t *start, int64_t n, v
 
 hipError_t launch_inflate(const float4 *in, float4 *out, const uint64_t *seg, const uint32_t *cols,
                           const int32_t *list, int64_t n, const int32_t *order, const int64_t *keys,
-                          const double *tri, const int64_t *bin_start, const int32_t *bin_items,
+                          const float *tri, const int64_t *bin_start, const int32_t *bin_items,
                           const LatticeGeom &g, double zeta, double *partials, double *sums,
                           hipStream_t s) {
     const int64_t nb = inflate_blocks(n);

@@ -103,13 +103,13 @@ hipError_t launch_taubin_half(const float4 *in, float4 *out, const uint64_t *seg
 // seg[t] = (rowptr[list[t]] << 32) | row length (rows below 2^32 entries)
 hipError_t launch_row_segments(const int64_t *rowptr, const int32_t *list, int64_t n, uint64_t *seg,
                                hipStream_t s);
-// Inflation (inflate.hip): triangles of the surface set in double with
-// sorted vertices, binned on the level-0 lattice.
+// Inflation (inflate.hip): triangles of the surface set (9 floats, sorted
+// vertices), binned on the level-0 lattice.
 hipError_t launch_strip_triangles(const Rec64 *rec, const int64_t *strip_off, const int64_t *tri_base,
-                                  int64_t n_strips, double *tri, hipStream_t s);
+                                  int64_t n_strips, float *tri, hipStream_t s);
 // pass 0 counts the triangles of each bin into count; pass 1 (count zeroed,
 // start its exclusive sum) places them into items.
-hipError_t launch_bin_triangles(const double *tri, int64_t n_tri, const LatticeGeom &g, int pass,
+hipError_t launch_bin_triangles(const float *tri, int64_t n_tri, const LatticeGeom &g, int pass,
                                 int32_t *count, const int64_t *start, int32_t *items, hipStream_t s);
 hipError_t exclusive_sum_bins(const int32_t *count, int64_t *start, int64_t n, void *tmp, size_t *tmp_bytes,
                               hipStream_t s);
@@ -117,7 +117,7 @@ hipError_t exclusive_sum_bins(const int32_t *count, int64_t *start, int64_t n, v
 // sums[0] = nodes moved, sums[1] = triangle tests.
 hipError_t launch_inflate(const float4 *in, float4 *out, const uint64_t *seg, const uint32_t *cols,
                           const int32_t *list, int64_t n, const int32_t *order, const int64_t *keys,
-                          const double *tri, const int64_t *bin_start, const int32_t *bin_items,
+                          const float *tri, const int64_t *bin_start, const int32_t *bin_items,
                           const LatticeGeom &g, double zeta, double *partials, double *sums,
                           hipStream_t s);
 int64_t inflate_blocks(int64_t n);
