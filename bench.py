@@ -46,6 +46,9 @@ def parse():
                     help="c3: then build the conforming transition mesh and check it")
     ap.add_argument("--smooth", action="store_true",
                     help="c3: conforming mesh, then Taubin smoothing (implies --conform)")
+    ap.add_argument("--cull", action="store_true",
+                    help="c3: label with bounding-box culling (pairs/s then counts the skipped "
+                         "pairs as well: an effective rate)")
     ap.add_argument("--inflate", action="store_true",
                     help="c3: conforming mesh, smoothing, then inflation (implies --smooth)")
     ap.add_argument("--smooth-iters", type=int, default=10,
@@ -296,7 +299,7 @@ def run_c3(args):
     mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = mesh.refine_relabel(ss, cfg.rounds, precision="fp32", rule=args.rule)
+    st = mesh.refine_relabel(ss, cfg.rounds, precision="fp32", rule=args.rule, cull=args.cull)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pairs = sum(r["n_pairs"] for r in st)
@@ -318,7 +321,8 @@ def run_c3(args):
     out_conform = _conform_c3(mesh, lat, rng) if post else None
     out_smooth = _smooth_c3(mesh, args.smooth_iters) if (args.smooth or args.inflate) else None
     out_inflate = _inflate_c3(mesh, ss) if args.inflate else None
-    return {"workload": "c3", "rule": args.rule, "triangles": cfg.n_tri, "rounds": st,
+    return {"workload": "c3", "rule": args.rule, "cull_bounds": bool(args.cull),
+            "triangles": cfg.n_tri, "rounds": st,
             "conform": out_conform, "smooth": out_smooth, "inflate": out_inflate,
             "leaves": n_leaves,
             "max_level": lv, "pairs": pairs, "wall_s": wall,

@@ -162,6 +162,12 @@ typedef struct sal_label_options {
     int32_t element_rule;     /* SAL_RULE_* for sal_refine_relabel; fixed by a mesh's
                                  first labeling (a later call with another rule
                                  fails with SAL_ERR_INVALID_ARG) */
+    int32_t cull_bounds;      /* 1: a wavefront whose points all lie strictly
+                                 outside the bounding box of a surface's vertices
+                                 skips that surface (they are outside its convex
+                                 hull, so w = 0 exactly and the labels are the
+                                 same); default 0.  sal_label_batch ignores it */
+    int32_t reserved;
 } sal_label_options;
 
 /* Fills the defaults listed above. */
@@ -183,6 +189,7 @@ typedef struct sal_label_stats {
                                   last kernel (launch-shape tuning excluded) */
     int32_t points_per_lane;   /* launch shape used (chosen by the tuner when 0 was asked) */
     int32_t block_waves;
+    int64_t n_pairs_culled;    /* pairs of n_pairs skipped by cull_bounds (w = 0 exactly) */
 } sal_label_stats;
 
 /* Labels n_points points (section 2.1.3: s = Omega / 4 pi, enclosed when

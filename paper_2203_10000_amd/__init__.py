@@ -48,7 +48,8 @@ class LabelOptions(ctypes.Structure):
                 ("threshold", ctypes.c_double), ("recheck_band", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("points_per_lane", ctypes.c_int32),
                 ("block_waves", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("element_rule", ctypes.c_int32)]
+                ("element_rule", ctypes.c_int32), ("cull_bounds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class LabelStats(ctypes.Structure):
@@ -58,7 +59,8 @@ class LabelStats(ctypes.Structure):
                 ("n_exact_fallbacks", ctypes.c_int64),
                 ("n_recheck_f64_terms", ctypes.c_int64), ("ms_pairloop", ctypes.c_float),
                 ("ms_recheck", ctypes.c_float), ("ms_total", ctypes.c_float),
-                ("points_per_lane", ctypes.c_int32), ("block_waves", ctypes.c_int32)]
+                ("points_per_lane", ctypes.c_int32), ("block_waves", ctypes.c_int32),
+                ("n_pairs_culled", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -201,7 +203,7 @@ RULE = {"centroid": 0, "four_nodes": 1}
 
 
 def label_options(precision="fp32", winding=None, threshold=0.5, band=1e-3, kappa=0.0,
-                  points_per_lane=0, block_waves=0, use_graph=False, rule="centroid"):
+                  points_per_lane=0, block_waves=0, use_graph=False, rule="centroid", cull=False):
     o = LabelOptions()
     lib().sal_label_options_default(ctypes.byref(o))
     o.precision = PREC[precision]
@@ -213,6 +215,7 @@ def label_options(precision="fp32", winding=None, threshold=0.5, band=1e-3, kapp
     o.block_waves = block_waves
     o.use_graph = 1 if use_graph else 0
     o.element_rule = RULE[rule]
+    o.cull_bounds = 1 if cull else 0
     return o
 
 

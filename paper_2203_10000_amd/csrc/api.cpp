@@ -96,6 +96,7 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     a.winding_type = winding ? opt.winding_type : SAL_WINDING_NONE;
     if (!winding) a.winding = nullptr;
     a.masks = masks;
+    a.cull = opt.cull_bounds ? 1 : 0;
     a.flag_list = ctx->flag_list;
     a.counters = ctx->counters;
     if (opt.precision == SAL_PREC_FP64) {
@@ -327,6 +328,7 @@ sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_
         stats->n_cond_flags = (int64_t)c[kCntCond];
         stats->n_exact_fallbacks = (int64_t)c[kCntExact];
         stats->n_recheck_f64_terms = (int64_t)c[kCntRecheckF64];
+        stats->n_pairs_culled = (int64_t)c[kCntCulled];
         SAL_HIP(hipEventElapsedTime(&stats->ms_pairloop, ctx->ev[0], ctx->ev[1]));
         SAL_HIP(hipEventElapsedTime(&stats->ms_total, ctx->ev[0], ctx->ev[2]));
         stats->ms_recheck = stats->ms_total - stats->ms_pairloop;

@@ -500,6 +500,7 @@ sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set
     key = mixd(key, opt.kappa);
     key = mix(key, (uint64_t)opt.points_per_lane);
     key = mix(key, (uint64_t)opt.block_waves);
+    key = mix(key, (uint64_t)opt.cull_bounds);
     for (int l = 0; l <= kMaxLevels; ++l) {
         key = mixp(key, m->key[l]);
         key = mixp(key, m->label[l]);

@@ -50,6 +50,9 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
     for (int j = 0; j < P; ++j) { lab[j] = 0; enc[j] = 0; flg[j] = 0; }
     uint32_t n_band = 0, n_cond = 0;
     const int lane = lane_id();
+    // pairs this lane's points skipped (a per-lane count: kept out of the
+    // scalar registers, whose count sets the occupancy)
+    uint32_t culled = 0;
 
     for (int k = 0; k < a.n_surf; ++k) {
         const int64_t rec_end = surf[k].rec_end;
@@ -59,8 +62,24 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
 #pragma unroll
         for (int j = 0; j < P; ++j) { S[j] = 0.0; cmask[j] = 0; }
 
-        surface_sum<P>(rec, surf[k].rec_begin, rec_end, px, py, pz, good_mask, kap, branch_cut, S,
-                       cmask);
+        // A point strictly outside the box of a closed surface's vertices is
+        // outside its convex hull: w = 0 exactly, no sum needed.
+        bool skip = false;
+        if (a.cull) {
+            bool out = true;
+#pragma unroll
+            for (int j = 0; j < P; ++j)
+                out = out && (!good[j] || px[j] < surf[k].lo[0] || px[j] > surf[k].hi[0] ||
+                              py[j] < surf[k].lo[1] || py[j] > surf[k].hi[1] ||
+                              pz[j] < surf[k].lo[2] || pz[j] > surf[k].hi[2]);
+            skip = ballot(!out) == 0;
+        }
+        if (skip) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) culled += good[j] ? (uint32_t)surf[k].n_tri : 0u;
+        } else
+            surface_sum<P>(rec, surf[k].rec_begin, rec_end, px, py, pz, good_mask, kap, branch_cut, S,
+                           cmask);
 
         // Section 2.1.3: enclosed when s = Omega / 4 pi >= T; later surfaces win.
 #pragma unroll
@@ -92,6 +111,11 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
         if (n_band) atomicAdd(&a.counters[kCntBand], (unsigned long long)n_band);
         if (n_cond) atomicAdd(&a.counters[kCntCond], (unsigned long long)n_cond);
     }
+    if (a.cull) {
+        uint64_t c = culled;
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+        if (lane == 0 && c) atomicAdd(&a.counters[kCntCulled], (unsigned long long)c);
+    }
 }
 
 // ------------------------------------------------------------------ float64
@@ -112,11 +136,21 @@ __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
     unsigned n_exact = 0;
     const CRec64 *rec = (const CRec64 *)a.rec64;
     const CSurf *surf = (const CSurf *)a.surf;
+    const uint64_t n_good = __popcll(ballot(good));
+    uint64_t culled = 0;
     for (int k = 0; k < a.n_surf; ++k) {
         const int64_t rec_end = surf[k].rec_end;
         double S = 0.0;
         int on = 0;
-        for (int64_t r = surf[k].rec_begin; r < rec_end;) {
+        // every point of the wavefront strictly outside the box: w = 0 exactly
+        bool skip = false;
+        if (a.cull) {
+            const bool out = !good || fx < surf[k].lo[0] || fx > surf[k].hi[0] || fy < surf[k].lo[1] ||
+                             fy > surf[k].hi[1] || fz < surf[k].lo[2] || fz > surf[k].hi[2];
+            skip = ballot(!out) == 0;
+        }
+        if (skip) culled += n_good * (uint64_t)surf[k].n_tri;
+        for (int64_t r = skip ? rec_end : surf[k].rec_begin; r < rec_end;) {
             double h[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) h[c] = rec[r].v[c];
@@ -149,6 +183,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
     if (a.masks && valid) a.masks[i] = good ? enc : 0ull;
     const uint64_t any = ballot(n_exact != 0);
     if (any) atomicAdd(&a.counters[kCntExact], (unsigned long long)n_exact);
+    if (culled && lane_id() == 0) atomicAdd(&a.counters[kCntCulled], (unsigned long long)culled);
 }
 
 __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n) {

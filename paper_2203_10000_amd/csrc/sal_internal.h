@@ -55,6 +55,7 @@ struct SurfaceDev {
     int64_t n_tri;
     int32_t label;
     int32_t pad;
+    float lo[3], hi[3];              // bounding box of the vertices (+-inf: never culled)
 };
 
 // A point with at least one (surface) winding number that the float32 pass
@@ -73,6 +74,7 @@ enum Counter {
     kCntExact = 3,     // exact-sign evaluations
     kCntRecheck = 4,   // pairs recomputed in FP64
     kCntRecheckF64 = 5,  // triangle terms of rechecked pairs evaluated in double
+    kCntCulled = 6,      // pairs skipped: every point of the wavefront outside the box
     kNumCounters = 8
 };
 
@@ -93,6 +95,8 @@ struct PairloopArgs {
     int32_t *__restrict__ labels;
     void *__restrict__ winding;   // [n_surf][n] float or double, or null
     int winding_type;
+    int cull;                     // skip a surface for a wavefront whose points are all
+                                  // strictly outside its bounding box (w = 0 exactly)
     unsigned long long *__restrict__ masks;  // [n] enclosure bits per point, or null
     FlagEntry *__restrict__ flag_list;  // capacity n
     unsigned long long *__restrict__ counters;
@@ -133,6 +137,8 @@ struct RecheckArgs {
     int32_t *__restrict__ labels;
     void *__restrict__ winding;
     int winding_type;
+    int cull;                     // skip a surface for a wavefront whose points are all
+                                  // strictly outside its bounding box (w = 0 exactly)
     unsigned long long *__restrict__ masks;  // [n] enclosure bits per point, or null
     const FlagEntry *__restrict__ flag_list;
     unsigned long long *__restrict__ counters;

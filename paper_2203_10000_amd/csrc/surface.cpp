@@ -201,6 +201,15 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
         sd.n_tri = hs.nt;
         sd.label = hs.label;
         sd.pad = 0;
+        for (int c = 0; c < 3; ++c) {
+            sd.lo[c] = INFINITY;
+            sd.hi[c] = -INFINITY;
+        }
+        for (int64_t v = 0; v < hs.nv; ++v)
+            for (int c = 0; c < 3; ++c) {
+                sd.lo[c] = std::min(sd.lo[c], hs.xyz[3 * v + c]);
+                sd.hi[c] = std::max(sd.hi[c], hs.xyz[3 * v + c]);
+            }
         total_tri += hs.nt;
         const float *V = hs.xyz;
         for (const Strip &s : strips) {
@@ -265,6 +274,10 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
         t.strip_end = s;
         t.n_tri = tris;
         t.label = 1;
+        for (int c = 0; c < 3; ++c) {
+            t.lo[c] = -INFINITY;
+            t.hi[c] = INFINITY;
+        }
         table.push_back(t);
     }
 

@@ -207,3 +207,43 @@ def test_auto_orient_gives_the_same_labels(ctx):
     a, _, _ = sal.label_points(ctx, ss1, dev(pts))
     b, _, _ = sal.label_points(ctx, ss2, dev(pts))
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bounding_box_culling_keeps_the_labels(ctx, precision):
+    """cull_bounds skips a surface for wavefronts whose points all lie
+    strictly outside its vertices' box (outside the convex hull, w = 0
+    exactly): labels still equal the oracle's, windings stay within the bar,
+    and the skipped pairs are counted."""
+    from oracle import kuhn
+    cfg = synth.config_small("head", cells=24, subdiv=3)
+    lat = cfg.lattice
+    pts = kuhn.centroids_mm(kuhn.level0_keys(lat.cells), lat.origin, lat.h)
+    want, w_ref = oracle.label(pts, cfg.surfaces, want_w=True)
+    tol = W_TOL_F32 if precision == "fp32" else W_TOL_F64
+    plain, w0, st0 = run(ctx, cfg.surfaces, pts, precision=precision, winding="f64")
+    got, w, st = run(ctx, cfg.surfaces, pts, precision=precision, winding="f64", cull=True)
+    assert np.array_equal(plain, want) and np.array_equal(got, want)
+    assert np.max(np.abs(w - w_ref)) < tol
+    assert st0["n_pairs_culled"] == 0
+    assert 0.1 * st["n_pairs"] < st["n_pairs_culled"] < st["n_pairs"]
+    # skipped pairs report exactly zero; the rest are the same computation
+    same = w != 0.0
+    assert np.array_equal(w[same], w0[same])
+    assert np.sum(w == 0.0) > 0
+
+
+def test_culling_in_refine_relabel_gives_the_same_mesh(ctx):
+    cfg = synth.config_small("head", cells=12, subdiv=3)
+    lat = cfg.lattice
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    out = []
+    for cull in (False, True):
+        for rule in ("centroid", "four_nodes"):
+            mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+            mesh.refine_relabel(ss, 2, rule=rule, cull=cull)
+            e = mesh.export(keys=True, labels=True, centroids=False)
+            torch.cuda.synchronize()
+            out.append((e["keys"].cpu().numpy(), e["labels"].cpu().numpy()))
+    for a, b in ((0, 2), (1, 3)):
+        assert np.array_equal(out[a][0], out[b][0]) and np.array_equal(out[a][1], out[b][1])
