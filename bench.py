@@ -516,7 +516,8 @@ def main():
 
     achieved = FLOPS_PER_PAIR * pairs / (ms_pairloop * 1e-3) / 1e12
     traffic = hbm_traffic(pairs)
-    roofline = {"bound": "alu", "kernel": "k_pairloop_f32<1>", "achieved": round(achieved, 2),
+    kernel = "k_pairloop_f32<%d, false>" % kstats[-1]["points_per_lane"]
+    roofline = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 2),
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": traffic, "flops_per_pair": FLOPS_PER_PAIR,
                 "kernel_ms": round(ms_pairloop, 3), "pairs_per_launch": pairs}

@@ -164,9 +164,12 @@ typedef struct sal_label_options {
                                  fails with SAL_ERR_INVALID_ARG) */
     int32_t cull_bounds;      /* 1: a wavefront whose points all lie strictly
                                  outside the bounding box of a surface's vertices
-                                 skips that surface (they are outside its convex
-                                 hull, so w = 0 exactly and the labels are the
-                                 same); default 0.  sal_label_batch ignores it */
+                                 (outside its convex hull: w = 0 exactly), or all
+                                 inside a ball that the surface does not cross
+                                 (w = that of the ball's centre, 0 or 1, found at
+                                 surface-set creation by the plain FP64 form),
+                                 skips that surface; the labels are the same.
+                                 Default 0.  sal_label_batch ignores it */
     int32_t reserved;
 } sal_label_options;
 

@@ -723,6 +723,10 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
         sal_label_options opt;
         sal_status st = resolve_options(opt_in, &opt);
         if (st != SAL_OK) return st;
+        if (opt.cull_bounds) {
+            SAL_HIP(hipSetDevice(ctx->device));
+            if ((st = ensure_surface_balls(ctx, set)) != SAL_OK) return st;
+        }
         opt.winding_type = SAL_WINDING_NONE;
         if (m->conformed)
             return set_error(SAL_ERR_INVALID_ARG, "the mesh was made conforming; it cannot be refined");

@@ -20,7 +20,10 @@ namespace {
 
 using namespace f32;
 
-template <int P>
+// CULL selects the form that tests each surface's box and ball first (see
+// below); without it the kernel has no trace of the test, so its register
+// budget (and occupancy) stays that of the plain walk.
+template <int P, bool CULL>
 __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
     const int64_t blk = (int64_t)blockIdx.x * blockDim.x * P;
     const int64_t n = a.n_dev ? *a.n_dev : a.n;
@@ -50,36 +53,48 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
     for (int j = 0; j < P; ++j) { lab[j] = 0; enc[j] = 0; flg[j] = 0; }
     uint32_t n_band = 0, n_cond = 0;
     const int lane = lane_id();
-    // pairs this lane's points skipped (a per-lane count: kept out of the
-    // scalar registers, whose count sets the occupancy)
-    uint32_t culled = 0;
 
     for (int k = 0; k < a.n_surf; ++k) {
-        const int64_t rec_end = surf[k].rec_end;
-        const int32_t slabel = surf[k].label;
         double S[P];
         uint64_t cmask[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) { S[j] = 0.0; cmask[j] = 0; }
 
         // A point strictly outside the box of a closed surface's vertices is
-        // outside its convex hull: w = 0 exactly, no sum needed.
+        // outside its convex hull (w = 0 exactly); a point inside a ball the
+        // surface does not cross has the winding number of the ball's centre.
+        // When every point of the wavefront qualifies the walk is skipped and
+        // S is set to give that w exactly (2 pi in double times kInv2Pi is
+        // 1.0); nothing of the test stays live across the walk.
         bool skip = false;
-        if (a.cull) {
-            bool out = true;
+        if (CULL) {
+            bool out = true, in = surf[k].ball_w >= 0;
 #pragma unroll
-            for (int j = 0; j < P; ++j)
+            for (int j = 0; j < P; ++j) {
                 out = out && (!good[j] || px[j] < surf[k].lo[0] || px[j] > surf[k].hi[0] ||
                               py[j] < surf[k].lo[1] || py[j] > surf[k].hi[1] ||
                               pz[j] < surf[k].lo[2] || pz[j] > surf[k].hi[2]);
-            skip = ballot(!out) == 0;
-        }
-        if (skip) {
+                const float dx = px[j] - surf[k].ball[0], dy = py[j] - surf[k].ball[1],
+                            dz = pz[j] - surf[k].ball[2];
+                in = in && (!good[j] || fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < surf[k].ball[3]);
+            }
+            const int fix = ballot(!out) == 0 ? 0 : (ballot(!in) == 0 ? surf[k].ball_w : -1);
+            if (fix >= 0) {
+                uint64_t n_good = 0;
 #pragma unroll
-            for (int j = 0; j < P; ++j) culled += good[j] ? (uint32_t)surf[k].n_tri : 0u;
-        } else
-            surface_sum<P>(rec, surf[k].rec_begin, rec_end, px, py, pz, good_mask, kap, branch_cut, S,
-                           cmask);
+                for (int j = 0; j < P; ++j) n_good += __popcll(good_mask[j]);
+                skip = true;
+#pragma unroll
+                for (int j = 0; j < P; ++j) S[j] = fix ? kTwoPi : 0.0;
+                // one atomic per skipped walk (a count carried through the
+                // loop would hold a register)
+                if (lane == 0 && n_good)
+                    atomicAdd(&a.counters[kCntCulled], (unsigned long long)(n_good * (uint64_t)surf[k].n_tri));
+            }
+        }
+        if (!skip)
+            surface_sum<P>(rec, surf[k].rec_begin, surf[k].rec_end, px, py, pz, good_mask, kap, branch_cut,
+                           S, cmask);
 
         // Section 2.1.3: enclosed when s = Omega / 4 pi >= T; later surfaces win.
 #pragma unroll
@@ -91,7 +106,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
             n_band += __popcll(ballot(band) & good_mask[j]);
             n_cond += __popcll(cmask[j]);
             if (band || cond) flg[j] |= 1ull << k;
-            if (in) { enc[j] |= 1ull << k; lab[j] = slabel; }
+            if (in) { enc[j] |= 1ull << k; lab[j] = surf[k].label; }
             if (a.winding && valid[j]) {
                 const int64_t o = (int64_t)k * n + idx[j];
                 const double wv = good[j] ? w : __builtin_nan("");
@@ -110,11 +125,6 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
     if (lane == 0) {
         if (n_band) atomicAdd(&a.counters[kCntBand], (unsigned long long)n_band);
         if (n_cond) atomicAdd(&a.counters[kCntCond], (unsigned long long)n_cond);
-    }
-    if (a.cull) {
-        uint64_t c = culled;
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-        if (lane == 0 && c) atomicAdd(&a.counters[kCntCulled], (unsigned long long)c);
     }
 }
 
@@ -142,12 +152,22 @@ __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
         const int64_t rec_end = surf[k].rec_end;
         double S = 0.0;
         int on = 0;
-        // every point of the wavefront strictly outside the box: w = 0 exactly
+        // every point of the wavefront strictly outside the box (w = 0
+        // exactly) or inside the ball (w = ball_w exactly)
         bool skip = false;
+        double wfix = 0.0;
         if (a.cull) {
+            const int32_t bw = surf[k].ball_w;
             const bool out = !good || fx < surf[k].lo[0] || fx > surf[k].hi[0] || fy < surf[k].lo[1] ||
                              fy > surf[k].hi[1] || fz < surf[k].lo[2] || fz > surf[k].hi[2];
-            skip = ballot(!out) == 0;
+            const float dx = fx - surf[k].ball[0], dy = fy - surf[k].ball[1], dz = fz - surf[k].ball[2];
+            const bool in = bw >= 0 && (!good || fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < surf[k].ball[3]);
+            if (ballot(!out) == 0) {
+                skip = true;
+            } else if (ballot(!in) == 0) {
+                skip = true;
+                wfix = (double)bw;
+            }
         }
         if (skip) culled += n_good * (uint64_t)surf[k].n_tri;
         for (int64_t r = skip ? rec_end : surf[k].rec_begin; r < rec_end;) {
@@ -167,7 +187,7 @@ __global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
             S += acc;
             r += m + 1;
         }
-        const double w = S * kInv2Pi;
+        const double w = skip ? wfix : S * kInv2Pi;
         if (on || w >= a.threshold) {
             lab = surf[k].label;
             enc |= 1ull << k;
@@ -199,10 +219,14 @@ hipError_t launch_pairloop_f32(const PairloopArgs &a, int ppl, int block_waves, 
     const int64_t per_block = (int64_t)threads * ppl;
     const int64_t blocks = (a.n + per_block - 1) / per_block;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    switch (ppl) {
-        case 1: k_pairloop_f32<1><<<dim3((unsigned)blocks), dim3(threads), 0, s>>>(a); break;
-        case 2: k_pairloop_f32<2><<<dim3((unsigned)blocks), dim3(threads), 0, s>>>(a); break;
-        case 4: k_pairloop_f32<4><<<dim3((unsigned)blocks), dim3(threads), 0, s>>>(a); break;
+    const dim3 g((unsigned)blocks), b(threads);
+    switch (ppl * 2 + (a.cull ? 1 : 0)) {
+        case 2: k_pairloop_f32<1, false><<<g, b, 0, s>>>(a); break;
+        case 3: k_pairloop_f32<1, true><<<g, b, 0, s>>>(a); break;
+        case 4: k_pairloop_f32<2, false><<<g, b, 0, s>>>(a); break;
+        case 5: k_pairloop_f32<2, true><<<g, b, 0, s>>>(a); break;
+        case 8: k_pairloop_f32<4, false><<<g, b, 0, s>>>(a); break;
+        case 9: k_pairloop_f32<4, true><<<g, b, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

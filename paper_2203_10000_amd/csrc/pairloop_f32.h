@@ -9,6 +9,7 @@ namespace sal {
 namespace f32 {
 
 constexpr double kInv2Pi = 0.15915494309189533577;
+constexpr double kTwoPi = 6.283185307179586;   // 2 pi in double: kTwoPi * kInv2Pi == 1.0
 constexpr float kPiF = 3.14159265358979323846f;
 
 // atan(t) for |t| <= 1/16 given t16 = 16 t:

@@ -51,6 +51,7 @@ struct sal_surface_set {
     std::vector<sal::SurfaceDev> host_table;
     std::vector<int64_t> host_strip_off;   // record index of every strip head
     std::vector<int32_t> host_strip_tris;  // triangles of every strip
+    bool balls_ready = false;              // ball_w of every surface known
 };
 
 namespace sal {
@@ -58,6 +59,11 @@ namespace sal {
 sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int32_t n,
                              uint32_t flags, sal_surface_set **out);
 void destroy_surface_set(sal_surface_set *set);
+
+// Finds the winding number of each surface's ball centre (plain FP64 form,
+// one launch per surface, synchronising the stream) the first time culling
+// is asked for; until then no ball is used.
+sal_status ensure_surface_balls(sal_context *ctx, const sal_surface_set *set);
 
 // Grows the context scratch to hold a flag list of n entries.
 sal_status ensure_flag_capacity(sal_context *ctx, int64_t n);

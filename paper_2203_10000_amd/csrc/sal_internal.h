@@ -56,6 +56,10 @@ struct SurfaceDev {
     int32_t label;
     int32_t pad;
     float lo[3], hi[3];              // bounding box of the vertices (+-inf: never culled)
+    float ball[4];                   // centre and squared radius of a ball the surface does
+                                     // not cross (radius shrunk for rounding)
+    int32_t ball_w;                  // winding number inside that ball (0 or 1), -1: none
+    int32_t pad2;
 };
 
 // A point with at least one (surface) winding number that the float32 pass
@@ -95,8 +99,9 @@ struct PairloopArgs {
     int32_t *__restrict__ labels;
     void *__restrict__ winding;   // [n_surf][n] float or double, or null
     int winding_type;
-    int cull;                     // skip a surface for a wavefront whose points are all
+    int cull;                     // skip a surface for a wavefront whose points all lie
                                   // strictly outside its bounding box (w = 0 exactly)
+                                  // or inside its ball (w = ball_w exactly)
     unsigned long long *__restrict__ masks;  // [n] enclosure bits per point, or null
     FlagEntry *__restrict__ flag_list;  // capacity n
     unsigned long long *__restrict__ counters;
@@ -137,8 +142,9 @@ struct RecheckArgs {
     int32_t *__restrict__ labels;
     void *__restrict__ winding;
     int winding_type;
-    int cull;                     // skip a surface for a wavefront whose points are all
+    int cull;                     // skip a surface for a wavefront whose points all lie
                                   // strictly outside its bounding box (w = 0 exactly)
+                                  // or inside its ball (w = ball_w exactly)
     unsigned long long *__restrict__ masks;  // [n] enclosure bits per point, or null
     const FlagEntry *__restrict__ flag_list;
     unsigned long long *__restrict__ counters;

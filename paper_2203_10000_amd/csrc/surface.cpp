@@ -1,9 +1,11 @@
 // Surface-set construction: validation of closed oriented manifolds, greedy
 // triangle strips, float32 / float64 strip records on the device.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <atomic>
 #include <unordered_map>
+#include <vector>
 
 #include "runtime.h"
 
@@ -169,6 +171,63 @@ double parity(const int32_t *f, int32_t p, int32_t q, int32_t r) {
     return -1.0;
 }
 
+// Squared distance from p to triangle (a, b, c), in double: the closest
+// point found by the Voronoi-region walk over vertices, edges and face
+// (Ericson, Real-Time Collision Detection, section 5.1.5).
+double dist2_point_triangle(const double p[3], const double a[3], const double b[3], const double c[3]) {
+    auto sub = [](const double *u, const double *v, double *o) {
+        for (int k = 0; k < 3; ++k) o[k] = u[k] - v[k];
+    };
+    auto dot = [](const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
+    double ab[3], ac[3], ap[3], q[3];
+    sub(b, a, ab);
+    sub(c, a, ac);
+    sub(p, a, ap);
+    const double d1 = dot(ab, ap), d2 = dot(ac, ap);
+    auto at = [&](double u, double v) {   // a + u ab + v ac
+        for (int k = 0; k < 3; ++k) q[k] = a[k] + u * ab[k] + v * ac[k];
+    };
+    if (d1 <= 0 && d2 <= 0) {
+        at(0, 0);
+    } else {
+        double bp[3];
+        sub(p, b, bp);
+        const double d3 = dot(ab, bp), d4 = dot(ac, bp);
+        if (d3 >= 0 && d4 <= d3) {
+            at(1, 0);
+        } else {
+            const double vc = d1 * d4 - d3 * d2;
+            if (vc <= 0 && d1 >= 0 && d3 <= 0) {
+                at(d1 / (d1 - d3), 0);
+            } else {
+                double cp[3];
+                sub(p, c, cp);
+                const double d5 = dot(ab, cp), d6 = dot(ac, cp);
+                if (d6 >= 0 && d5 <= d6) {
+                    at(0, 1);
+                } else {
+                    const double vb = d5 * d2 - d1 * d6;
+                    if (vb <= 0 && d2 >= 0 && d6 <= 0) {
+                        at(0, d2 / (d2 - d6));
+                    } else {
+                        const double va = d3 * d6 - d5 * d4;
+                        if (va <= 0 && (d4 - d3) >= 0 && (d5 - d6) >= 0) {
+                            const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+                            at(1 - w, w);
+                        } else {
+                            const double den = 1.0 / (va + vb + vc);
+                            at(vb * den, vc * den);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    double d[3];
+    sub(p, q, d);
+    return dot(d, d);
+}
+
 }  // namespace
 
 sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int32_t n,
@@ -210,6 +269,31 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
                 sd.lo[c] = std::min(sd.lo[c], hs.xyz[3 * v + c]);
                 sd.hi[c] = std::max(sd.hi[c], hs.xyz[3 * v + c]);
             }
+        // a ball about the vertex mean (rounded to float) that the surface
+        // does not cross: radius = distance to the nearest triangle, less a
+        // margin far above the rounding of the device's float distance test
+        {
+            double m[3] = {0, 0, 0};
+            for (int64_t v = 0; v < hs.nv; ++v)
+                for (int c = 0; c < 3; ++c) m[c] += hs.xyz[3 * v + c];
+            double cen[3];
+            for (int c = 0; c < 3; ++c) {
+                sd.ball[c] = (float)(m[c] / (double)hs.nv);
+                cen[c] = sd.ball[c];
+            }
+            double r2 = INFINITY;
+            for (int64_t t = 0; t < hs.nt; ++t) {
+                double P[3][3];
+                for (int q = 0; q < 3; ++q)
+                    for (int c = 0; c < 3; ++c) P[q][c] = hs.xyz[3 * (int64_t)hs.tri[3 * t + q] + c];
+                r2 = std::min(r2, dist2_point_triangle(cen, P[0], P[1], P[2]));
+            }
+            const double scale = std::max({std::fabs(cen[0]), std::fabs(cen[1]), std::fabs(cen[2])});
+            const double r = std::sqrt(r2) - 1e-5 * (std::sqrt(r2) + scale);
+            sd.ball[3] = r > 0 ? (float)(r * r * (1.0 - 1e-6)) : 0.0f;
+            sd.ball_w = -1;   // set by ensure_surface_balls, on first use
+            sd.pad2 = 0;
+        }
         total_tri += hs.nt;
         const float *V = hs.xyz;
         for (const Strip &s : strips) {
@@ -278,6 +362,7 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
             t.lo[c] = -INFINITY;
             t.hi[c] = INFINITY;
         }
+        t.ball_w = -1;
         table.push_back(t);
     }
 
@@ -312,6 +397,58 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
     }
     set->tune_surf = set->surf + n;
     *out = set;
+    return SAL_OK;
+}
+
+sal_status ensure_surface_balls(sal_context *ctx, const sal_surface_set *cset) {
+    auto *set = const_cast<sal_surface_set *>(cset);
+    if (set->balls_ready) return SAL_OK;
+    const int n = set->n_surf;
+    std::vector<SurfaceDev> table = set->host_table;
+    std::vector<float> c(3 * (size_t)n);
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) c[(size_t)(a * n + i)] = table[(size_t)i].ball[a];
+    float *dc = nullptr;
+    int32_t *dl = nullptr;
+    unsigned long long *dm = nullptr;
+    std::vector<unsigned long long> masks((size_t)n, 0);
+    hipError_t e = hipMalloc((void **)&dc, c.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&dl, (size_t)n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&dm, (size_t)n * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemcpy(dc, c.data(), c.size() * sizeof(float), hipMemcpyHostToDevice);
+    // each centre against its own surface only: one FP64 launch per surface
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        PairloopArgs a{};
+        a.rec32 = set->rec32;
+        a.rec64 = set->rec64;
+        a.surf = set->surf + i;
+        a.n_surf = 1;
+        a.x = dc + i;
+        a.y = dc + n + i;
+        a.z = dc + 2 * n + i;
+        a.n = 1;
+        a.kappa = 0.03125f;
+        a.threshold = 0.5;
+        a.band = 0.0;
+        a.labels = dl + i;
+        a.masks = dm + i;
+        a.counters = ctx->counters;
+        e = launch_pairloop_f64(a, 1, ctx->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(masks.data(), dm, (size_t)n * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (dc) (void)hipFree(dc);
+    if (dl) (void)hipFree(dl);
+    if (dm) (void)hipFree(dm);
+    if (e != hipSuccess) return hip_error(e, "surface ball centres");
+    for (int i = 0; i < n; ++i) {
+        SurfaceDev &sd = table[(size_t)i];
+        sd.ball_w = sd.ball[3] > 0.0f ? (int32_t)(masks[(size_t)i] & 1ull) : -1;
+    }
+    e = hipMemcpy(set->surf, table.data(), (size_t)n * sizeof(SurfaceDev), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "hipMemcpy(surface table)");
+    set->host_table = table;
+    set->balls_ready = true;
     return SAL_OK;
 }
 

@@ -213,8 +213,9 @@ def test_auto_orient_gives_the_same_labels(ctx):
 def test_bounding_box_culling_keeps_the_labels(ctx, precision):
     """cull_bounds skips a surface for wavefronts whose points all lie
     strictly outside its vertices' box (outside the convex hull, w = 0
-    exactly): labels still equal the oracle's, windings stay within the bar,
-    and the skipped pairs are counted."""
+    exactly) or inside a ball the surface does not cross (w = 1 or 0 exactly):
+    labels still equal the oracle's, windings stay within the bar, and the
+    skipped pairs are counted."""
     from oracle import kuhn
     cfg = synth.config_small("head", cells=24, subdiv=3)
     lat = cfg.lattice
@@ -227,10 +228,10 @@ def test_bounding_box_culling_keeps_the_labels(ctx, precision):
     assert np.max(np.abs(w - w_ref)) < tol
     assert st0["n_pairs_culled"] == 0
     assert 0.1 * st["n_pairs"] < st["n_pairs_culled"] < st["n_pairs"]
-    # skipped pairs report exactly zero; the rest are the same computation
-    same = w != 0.0
+    # skipped pairs report exactly 0 or 1; the rest are the same computation
+    same = (w != 0.0) & (w != 1.0)
     assert np.array_equal(w[same], w0[same])
-    assert np.sum(w == 0.0) > 0
+    assert np.sum(w == 0.0) > 0 and np.sum(w == 1.0) > 0
 
 
 def test_culling_in_refine_relabel_gives_the_same_mesh(ctx):
