@@ -99,3 +99,115 @@ def test_c5_surfaces_near_surface_points(ctx):
     idx = _sample(rng, len(lab), 1200)
     want = oracle.label(np.ascontiguousarray(cfg.points[:, idx]), cfg.surfaces)
     assert np.array_equal(lab[idx], want)
+
+
+def _tet_volumes6(pts, tets, chunk=1 << 24):
+    v6 = torch.empty(len(tets), dtype=torch.int64, device=tets.device)
+    for lo in range(0, len(tets), chunk):
+        p = pts[tets[lo:lo + chunk]]
+        a, b, c = p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]
+        v6[lo:lo + len(p)] = (a[:, 0] * (b[:, 1] * c[:, 2] - b[:, 2] * c[:, 1])
+                              - a[:, 1] * (b[:, 0] * c[:, 2] - b[:, 2] * c[:, 0])
+                              + a[:, 2] * (b[:, 0] * c[:, 1] - b[:, 1] * c[:, 0]))
+    return v6
+
+
+def _crossing_distance(p, q, tri):
+    """Smallest distance from p along p -> q to a crossing with any triangle
+    (float64 torch tensors; tri [T, 3, 3]), by solving the 3x3 system
+    p + t (q - p) = v0 + u (v1 - v0) + v (v2 - v0) for every triangle; inf if
+    none.  Independent of the library's binned Moller-Trumbore test."""
+    d = q - p
+    m = torch.stack([d.expand(len(tri), 3), tri[:, 0] - tri[:, 1], tri[:, 0] - tri[:, 2]], 2)
+    rhs = (tri[:, 0] - p).unsqueeze(2)
+    ok = torch.linalg.det(m).abs() > 1e-12
+    sol = torch.linalg.solve(m[ok], rhs[ok]).squeeze(2)
+    t, u, v = sol[:, 0], sol[:, 1], sol[:, 2]
+    hit = (u >= -1e-9) & (v >= -1e-9) & (u + v <= 1 + 1e-9) & (t >= -1e-9) & (t <= 1 + 1e-9)
+    if not bool(hit.any()):
+        return float("inf")
+    return float(t[hit].min().clamp(min=0) * torch.linalg.norm(d))
+
+
+def test_c3_full_size_post_processing(ctx):
+    """c3 with the four-node rule (1.04e8 leaves): the conforming mesh tiles
+    the box exactly with positive volumes and no node inside a sampled edge;
+    smoothing keeps the box nodes and stops by the paper's ratios; inflation
+    moves only interface nodes, each along one of its edges by zeta times the
+    distance to the nearest crossing, checked on a sample against every
+    triangle by an independent linear solve."""
+    cfg = synth.config_c3()
+    lat = cfg.lattice
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    mesh.refine_relabel(ss, cfg.rounds, rule="four_nodes")
+    info = mesh.conform()
+    e = mesh.export_conforming()
+    keys = e["node_keys"]
+    m = 0x1FFFFF
+    grid = torch.stack([(keys >> 42) & m, (keys >> 21) & m, keys & m], 1)
+    tets = e["tets"].long()
+    v6 = _tet_volumes6(grid, tets)
+    assert bool((v6 > 0).all())
+    assert int(v6.sum()) == 6 * int(np.prod(np.array(lat.cells, dtype=np.int64) * 8))
+    rng = np.random.default_rng(601)
+    idx = torch.from_numpy(rng.choice(len(tets), 100000, replace=False)).to(tets.device)
+    p = grid[tets[idx]]
+    for i, j in [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]:
+        s2 = p[:, i] + p[:, j]
+        even = (s2 % 2 == 0).all(1)
+        mk = ((s2[:, 0] // 2) << 42) | ((s2[:, 1] // 2) << 21) | (s2[:, 2] // 2)
+        pos = torch.searchsorted(keys, mk).clamp(max=len(keys) - 1)
+        assert not bool((even & (keys[pos] == mk)).any())
+    del v6, p
+
+    # node classes from the tetrahedra's labels (interface: two or more labels)
+    lab = e["labels"].long()
+    n = len(keys)
+    lo = torch.full((n,), 1 << 40, dtype=torch.int64, device=keys.device)
+    hi = torch.full((n,), -(1 << 40), dtype=torch.int64, device=keys.device)
+    for c in range(4):
+        lo.scatter_reduce_(0, tets[:, c], lab, "amin")
+        hi.scatter_reduce_(0, tets[:, c], lab, "amax")
+    interface = lo != hi
+    lim = torch.tensor([c * 8 for c in lat.cells], device=keys.device)
+    box = ((grid == 0) | (grid == lim)).any(1)
+
+    x0 = e["xyz"].clone()
+    st = mesh.smooth()
+    x1 = mesh.export_conforming()["xyz"]
+    assert st["iters_surface"] == 1 and st["ratio_surface"] <= 0.1
+    assert st["iters_volume"] == 1 and st["ratio_volume"] <= 0.9
+    assert st["n_surface_nodes"] == int((interface & ~box).sum())
+    assert torch.equal(x1[box], x0[box]) and bool(torch.isfinite(x1).all())
+    assert bool((x1 != x0).any(1)[~box].any())
+
+    inf_info = mesh.inflate(ss, 0.05)
+    x2 = mesh.export_conforming()["xyz"]
+    moved = (x2 != x1).any(1)
+    assert not bool((moved & ~(interface & ~box)).any())
+    assert inf_info["n_candidates"] == int((interface & ~box).sum())
+    assert 0 < int(moved.sum()) <= inf_info["n_moved"]
+    tri = torch.from_numpy(np.concatenate([s.v.astype(np.float64)[s.f] for s in cfg.surfaces])).to(
+        keys.device)
+    cand = torch.nonzero(moved).squeeze(1).cpu().numpy()
+    for i in rng.choice(cand, 40, replace=False):
+        inc = tets[(tets == int(i)).any(1)].reshape(-1).unique()
+        nbrs = inc[inc != int(i)].tolist()
+        p0 = x1[int(i)].double()
+        dist = [_crossing_distance(p0, x1[jn].double(), tri) for jn in nbrs]
+        best = min(dist)
+        assert np.isfinite(best)
+        step = x2[int(i)].double() - p0
+        # float32 positions near 100 mm round to within 4e-6 mm: the step is
+        # 0.05 d long and runs along an edge whose crossing is (nearly) the
+        # nearest, to within a few of those roundings
+        assert abs(float(torch.linalg.norm(step)) - 0.05 * best) <= 4e-5
+        along = []
+        for jn, dj in zip(nbrs, dist):
+            if dj <= best * (1 + 1e-6) + 1e-9:
+                edge = x1[jn].double() - p0
+                unit = edge / torch.linalg.norm(edge)
+                along.append(float(torch.linalg.norm(torch.cross(step, unit, dim=0))) <= 4e-5
+                             and float(torch.dot(step, unit)) > 0)
+        assert any(along)
