@@ -620,6 +620,28 @@ struct DevScratch {
     }
 };
 
+// A device buffer reused across the rounds of one call, reallocated (with a
+// quarter to spare) only when a round needs more than it holds.
+template <typename T>
+struct GrowBuf {
+    T *p = nullptr;
+    int64_t cap = 0;
+    ~GrowBuf() {
+        if (p) (void)hipFree(p);
+    }
+    sal_status need(int64_t n) {
+        if (n <= cap) return SAL_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        const int64_t c = n + n / 4 + 1024;
+        if (hipMalloc((void **)&p, (size_t)c * sizeof(T)) != hipSuccess)
+            return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conform)");
+        cap = c;
+        return SAL_OK;
+    }
+};
+
 }  // namespace
 }  // namespace sal
 
@@ -849,12 +871,13 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
         };
         if ((st = rebuild()) != SAL_OK) return st;
         int rounds = 0;
+        GrowBuf<int32_t> red_buf;              // red leaves of a round
+        GrowBuf<unsigned long long> fresh_buf; // vertices new in a round
         for (;;) {
-            DevScratch iter;             // freed at the end of each closure round
             int64_t off[kMaxLevels + 2] = {0};
             for (int l = 0; l <= m->max_level; ++l) off[l + 1] = off[l] + m->n[l];
-            int32_t *red_list = nullptr;
-            if ((st = iter.get(&red_list, off[m->max_level + 1])) != SAL_OK) return st;
+            if ((st = red_buf.need(off[m->max_level + 1])) != SAL_OK) return st;
+            int32_t *red_list = red_buf.p;
             int64_t red[kMaxLevels + 1] = {0}, total_red = 0;
             for (int l = 0; l <= m->max_level; ++l) {
                 CompactSrc src{m->flag[l], nullptr, 0x80};
@@ -889,8 +912,8 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
             // the new vertices are edge midpoints of the split leaves (6 each)
             int64_t fcap = 1024;
             while (fcap < 12 * total_red) fcap <<= 1;
-            unsigned long long *fresh = nullptr;
-            if ((st = iter.get(&fresh, fcap)) != SAL_OK) return st;
+            if ((st = fresh_buf.need(fcap)) != SAL_OK) return st;
+            unsigned long long *fresh = fresh_buf.p;
             SAL_HIP(launch_fill_u64(fresh, ~0ull, fcap, s));
             SAL_HIP(launch_fill_u64(counters, 0ull, 2, s));
             LevelPtrs L = ptrs(m);
@@ -915,7 +938,7 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
                 SAL_HIP(launch_pattern_fresh(L, m->g, l, old_n[l], fresh, fcap, s));
                 SAL_HIP(launch_pattern_full(L, m->g, l, old_n[l], m->n[l] - old_n[l], set, cap, s));
             }
-            SAL_HIP(hipStreamSynchronize(s));   // before this round's scratch is freed
+            SAL_HIP(hipStreamSynchronize(s));
         }
 
         // the leaves in index order per level
