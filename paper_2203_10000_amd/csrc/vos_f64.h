@@ -53,20 +53,32 @@ __device__ __forceinline__ void f64_strip_head(StripF64 &s, const double *h, con
     f64_strip_window(s, h, h + 3, p);
 }
 
-// Out-of-line exact resolution of a triangle whose N sign is uncertain.
-// Returns the corrected N (exact sign, magnitude kept) or 0 with *coplanar set.
-__device__ __noinline__ double f64_exact_n(const float *praw, const float *X, const float *Y,
-                                           const float *Z, double sigma, double n_val,
-                                           int *on, bool *coplanar) {
-    const int o = exact_orient3d(praw, X, Y, Z) * (sigma > 0.0 ? 1 : -1);
+// Result of the exact resolution: the corrected N, and flags (bit 0: the
+// point is on the triangle's plane, bit 1: inside the closed triangle).
+struct ExactN {
+    double n;
+    int flags;
+};
+
+// Out-of-line exact resolution of a triangle whose N sign is uncertain: the
+// corrected N (exact sign, magnitude kept), or 0 with the coplanar flag.
+// Coordinates come by value, so the caller's strip window stays in registers
+// (a pointer argument would place it in scratch memory for every step).
+__device__ __noinline__ ExactN f64_exact_n(float px, float py, float pz, float x0, float x1, float x2,
+                                           float y0, float y1, float y2, float z0, float z1, float z2,
+                                           double sigma, double n_val) {
+    const float P[3] = {px, py, pz}, X[3] = {x0, x1, x2}, Y[3] = {y0, y1, y2}, Z[3] = {z0, z1, z2};
+    const int o = exact_orient3d(P, X, Y, Z) * (sigma > 0.0 ? 1 : -1);
+    ExactN r;
     if (o == 0) {
-        *coplanar = true;
-        if (exact_in_triangle(praw, X, Y, Z)) *on = 1;
-        return 0.0;
+        r.n = 0.0;
+        r.flags = 1 | (exact_in_triangle(P, X, Y, Z) ? 2 : 0);
+        return r;
     }
-    *coplanar = false;
     const double mag = n_val != 0.0 ? fabs(n_val) : 2.2250738585072014e-308;
-    return o > 0 ? mag : -mag;
+    r.n = o > 0 ? mag : -mag;
+    r.flags = 0;
+    return r;
 }
 
 // One strip step: the triangle (X, Y, Z) with Z and its normal in record t.
@@ -83,11 +95,12 @@ __device__ __forceinline__ double f64_strip_tri(StripF64 &s, const double *t, co
     double half = 0.0;
     // |N - N_exact| <= ~10 eps |Z - p| |B - A| |C - A|; 32 eps leaves margin.
     if (fabs(num) <= 32.0 * 1.1102230246251565e-16 * r2 * t[6]) {
-        const float Z[3] = {(float)t[0], (float)t[1], (float)t[2]};
-        bool coplanar = false;
-        num = f64_exact_n(praw, s.X, s.Y, Z, t[7], num, on, &coplanar);
+        const ExactN r = f64_exact_n(praw[0], praw[1], praw[2], s.X[0], s.X[1], s.X[2], s.Y[0], s.Y[1],
+                                     s.Y[2], (float)t[0], (float)t[1], (float)t[2], t[7], num);
+        num = r.n;
+        if (r.flags & 2) *on = 1;
         *n_exact += 1;
-        if (!coplanar) half = atan2(num, den);
+        if (!(r.flags & 1)) half = atan2(num, den);
     } else {
         half = atan2(num, den);
     }
