@@ -130,8 +130,10 @@ __global__ __launch_bounds__(512) void k_pairloop_f32(PairloopArgs a) {
 
 // ------------------------------------------------------------------ float64
 // The plain FP64 form: one point per lane, every triangle in double with the
-// exact-sign guard; labels are final.
-__global__ __launch_bounds__(512) void k_pairloop_f64(PairloopArgs a) {
+// exact-sign guard; labels are final.  Held to 128 VGPRs (4 waves per SIMD):
+// the few spills this costs sit outside the triangle loop (measured on c2:
+// 147 VGPRs / 3 waves 247 G pairs/s, 128 / 4 waves 259, 102 / 5 waves 53).
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_pairloop_f64(PairloopArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = a.n_dev ? *a.n_dev : a.n;
     if ((int64_t)blockIdx.x * blockDim.x >= n) return;
