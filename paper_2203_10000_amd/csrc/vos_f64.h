@@ -101,6 +101,17 @@ __device__ __forceinline__ double f64_strip_tri(StripF64 &s, const double *t, co
         if (r.flags & 2) *on = 1;
         *n_exact += 1;
         if (!(r.flags & 1)) half = atan2(num, den);
+    } else if (den > 16.0 * fabs(num)) {
+        // |N / D| < 1/16 with D > 0: atan2(N, D) = atan(t), t = N / D, by its
+        // Taylor series to t^13 (the first omitted term is below 1e-18 t)
+        const double t = num / den, q = t * t;
+        double poly = 1.0 / 13.0;
+        poly = fma(poly, q, -1.0 / 11.0);
+        poly = fma(poly, q, 1.0 / 9.0);
+        poly = fma(poly, q, -1.0 / 7.0);
+        poly = fma(poly, q, 1.0 / 5.0);
+        poly = fma(poly, q, -1.0 / 3.0);
+        half = fma(t * q, poly, t);
     } else {
         half = atan2(num, den);
     }
