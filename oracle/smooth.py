@@ -69,6 +69,8 @@ def taubin(x, adj, movable, lam, mu, xi, max_iter):
     (positions, iterations run, ratio of each iteration)."""
     x = np.array(x, dtype=np.float64)
     mv = np.asarray(movable, dtype=bool)
+    if not mv.any():
+        return x, 0, []          # nothing to smooth: the phase runs no iteration
     norm0 = np.linalg.norm(x[mv])
     ratios = []
     for _ in range(max_iter):

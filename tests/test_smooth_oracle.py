@@ -91,6 +91,7 @@ def test_unrefined_kuhn_lattice_interior_does_not_move():
     y, info = smooth.smooth_mesh(ids, lab, xyz, box)
     np.testing.assert_allclose(y, xyz, rtol=0, atol=1e-12)
     assert info["n_surface_nodes"] == 0 and info["iters_volume"] == 1
+    assert info["iters_surface"] == 0
 
 
 def test_interface_of_two_labels_split_by_a_lattice_plane():
