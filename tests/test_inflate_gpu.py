@@ -106,3 +106,32 @@ def test_smoothing_then_inflation_matches_the_oracle_pipeline(ctx):
     tol = 2.0 ** -24 * np.abs(want).max() * 8
     print("max err %.3g, nodes above %.3g: %d of %d" % (err.max(), tol, np.sum(err > tol), len(err)))
     assert np.sum(err > tol) <= max(1, len(err) // 1000)
+
+
+def test_mesh_without_an_interface(ctx):
+    """A lattice that the surface does not reach: every label is 0, the mesh
+    stays the Kuhn lattice, the surface phase of the smoothing has nothing to
+    move (no iteration), the volume phase leaves the symmetric interior where
+    it is, and inflation has no candidate."""
+    surfaces = synth.config_small("sphere", cells=4, subdiv=1).surfaces
+    lat = synth.Lattice(origin=(150.0, 150.0, 150.0), h=25.0, cells=(4, 5, 3))
+    cfg = synth.Config("outside", surfaces, lattice=lat, precision="fp32")
+    nodes, ids, lab, xyz0 = _oracle_mesh(cfg, 2)
+    assert not np.any(lab)
+    box = smooth.on_box(nodes, lat.cells)
+    want, winfo = smooth.smooth_mesh(ids, lab, xyz0.astype(np.float64), box)
+    assert winfo["iters_surface"] == 0 and winfo["n_surface_edges"] == 0
+    mesh, ss = _device(ctx, cfg, 2)
+    out = mesh.export_conforming()
+    assert np.array_equal(out["node_keys"].cpu().numpy(), nodes)
+    assert np.array_equal(out["xyz"].cpu().numpy(), xyz0)
+    sinfo = mesh.smooth()
+    print(sinfo, flush=True)
+    for k in ("n_edges", "n_surface_edges", "n_surface_nodes", "n_volume_nodes",
+              "iters_surface", "iters_volume"):
+        assert sinfo[k] == winfo[k], k
+    got = mesh.export_conforming()["xyz"].cpu().numpy().astype(np.float64)
+    assert np.abs(got - want).max() <= 2.0 ** -24 * np.abs(want).max() * 8
+    info = mesh.inflate(ss, 0.05)
+    assert info["n_candidates"] == 0 and info["n_moved"] == 0
+    assert np.array_equal(mesh.export_conforming()["xyz"].cpu().numpy().astype(np.float64), got)
