@@ -312,7 +312,10 @@ typedef struct sal_conform_info {
  * sal_tet_mesh_export lists them.  After this call the mesh cannot be refined
  * again (SAL_ERR_INVALID_ARG), nor made conforming twice.
  *   info  NULL, or filled after synchronising
- * Errors: SAL_ERR_CAPACITY above 2^31 tetrahedron corners; SAL_ERR_OUT_OF_MEMORY. */
+ * Errors: SAL_ERR_CAPACITY above 2^31 tetrahedron corners; SAL_ERR_OUT_OF_MEMORY.
+ * After such an error the mesh is not conforming, but its leaf set may already
+ * hold closure splits (children with their parent's label); calling this
+ * function again resumes the closure from there. */
 sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *mesh, sal_conform_info *info);
 
 /* Copies the conforming mesh into caller device buffers (each may be NULL):

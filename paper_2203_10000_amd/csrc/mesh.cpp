@@ -827,10 +827,25 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
 }
 
 sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_info *info) {
+    // Frees the conforming-mesh arrays unless the call completes, so a call
+    // that fails part way leaves none behind for a later call to overwrite.
+    struct DropUnlessDone {
+        sal_tet_mesh *m;
+        bool done = false;
+        ~DropUnlessDone() {
+            if (done) return;
+            int32_t **i32[] = {&m->conf_ids, &m->conf_labels};
+            for (int32_t **p : i32)
+                if (*p) (void)hipFree(*p), *p = nullptr;
+            if (m->conf_keys) (void)hipFree(m->conf_keys), m->conf_keys = nullptr;
+            if (m->conf_xyz) (void)hipFree(m->conf_xyz), m->conf_xyz = nullptr;
+        }
+    };
     try {
         if (!ctx || !m) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
         if (m->device != ctx->device) return set_error(SAL_ERR_INVALID_ARG, "mesh lives on another device");
         if (m->conformed) return set_error(SAL_ERR_INVALID_ARG, "the mesh is already conforming");
+        DropUnlessDone guard{m};
         SAL_HIP(hipSetDevice(ctx->device));
         hipStream_t s = ctx->stream;
         sal_status st;
@@ -1023,6 +1038,7 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
         m->conf_tets = n_tets;
         m->conf_nodes = n_nodes;
         m->conformed = true;
+        guard.done = true;
         if (info) {
             std::memset(info, 0, sizeof(*info));
             info->n_tets = n_tets;

@@ -12,12 +12,12 @@ constexpr double kInv2Pi = 0.15915494309189533577;
 constexpr double kTwoPi = 6.283185307179586;   // 2 pi in double: kTwoPi * kInv2Pi == 1.0
 constexpr float kPiF = 3.14159265358979323846f;
 
-// atan(t) for |t| <= 1/16 given t16 = 16 t:
-//   t16 (1/16 - t16^2 / (3 16^3) + t16^4 / (5 16^5)),
-// the Taylor series to t^5; the first omitted term is below 1e-8 t.
-constexpr float kA0 = 0.0625f;
-constexpr float kA1 = -8.1380208333e-05f;   // -1 / (3 * 4096)
-constexpr float kA2 = 1.9073486328e-07f;    //  1 / (5 * 1048576)
+// atan(t) for |t| <= 1/32 given u = 32 t (the record normals carry the
+// factor 32):  u (1/32 - u^2 / (3 32^3)), the Taylor series to t^3; the first
+// omitted term, t^5 / 5, is below 2e-7 t.
+constexpr float kA0 = 0.03125f;
+constexpr float kA1 = -1.0172526042e-05f;   // -1 / (3 * 32768)
+static_assert(kNScale == 32.0f, "series constants assume normals scaled by 32");
 
 __device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
@@ -113,20 +113,18 @@ __device__ __forceinline__ void f32_step(const Vtx (&O)[P], const Vtx (&N)[P], V
         r2[j] = __builtin_amdgcn_sqrtf(fmaf(x2[j], x2[j], fmaf(y2[j], y2[j], z2[j] * z2[j])));
         e02[j] = fmaf(O[j].x, x2[j], fmaf(O[j].y, y2[j], O[j].z * z2[j]));
         e12[j] = fmaf(N[j].x, x2[j], fmaf(N[j].y, y2[j], N[j].z * z2[j]));
-        nn[j] = fmaf(x2[j], q3, fmaf(y2[j], q4, z2[j] * q5));            // 16 N
+        nn[j] = fmaf(x2[j], q3, fmaf(y2[j], q4, z2[j] * q5));            // 32 N
         mm[j] = rr01[j] * r2[j];                                         // |a||b||c|
         dd[j] = fmaf(e12[j], O[j].r, fmaf(e02[j], N[j].r, fmaf(e01[j], r2[j], mm[j])));
-        // small-angle path: |N/D| < 1/16, D > kappa |a||b||c|, D > 5 |n| |c|
+        // small-angle path: |N/D| < 1/32, D > kappa |a||b||c|, D > 5 |n| |c|
         const float lim = fmaf(q7, r2[j], fmaf(kap, mm[j], fabsf(nn[j])));
         near |= ballot(!(dd[j] > lim)) & good_mask[j];
     }
     if (near == 0) {
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            const float t16 = nn[j] * __builtin_amdgcn_rcpf(dd[j]);
-            const float s = t16 * t16;
-            const float pl = fmaf(fmaf(kA2, s, kA1), s, kA0);
-            acc[j] = fmaf(t16, pl, acc[j]);
+            const float u = nn[j] * __builtin_amdgcn_rcpf(dd[j]);
+            acc[j] = fmaf(u, fmaf(kA1, u * u, kA0), acc[j]);
         }
     } else {
 #pragma unroll

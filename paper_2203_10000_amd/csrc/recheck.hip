@@ -179,16 +179,16 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_rc_pairs(RecheckArgs a) {
                 const float cr = __builtin_amdgcn_sqrtf(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
                 const float e02 = fmaf(ax, cx, fmaf(ay, cy, az * cz));
                 const float e12 = fmaf(bx, cx, fmaf(by, cy, bz * cz));
-                const float nn = fmaf(cx, q3, fmaf(cy, q4, cz * q5));   // 16 N
+                const float nn = fmaf(cx, q3, fmaf(cy, q4, cz * q5));   // 32 N
                 const float mm = rr01 * cr;
                 const float dd = fmaf(e12, ar, fmaf(e02, br, fmaf(e01, cr, mm)));
                 const float lim = fmaf(q7, cr, fmaf(kap, mm, fabsf(nn)));
                 // Per-lane choice (not wave-uniform as in the pair loop): a pair's
                 // terms must not depend on which pairs share its wavefront.
                 if (dd > lim) {
-                    const float t16 = nn * __builtin_amdgcn_rcpf(dd);
-                    const float s2 = t16 * t16;
-                    accf = fmaf(t16, fmaf(fmaf(mixed::kA2, s2, mixed::kA1), s2, mixed::kA0), accf);
+                    const float u = nn * __builtin_amdgcn_rcpf(dd);
+                    const float s2 = u * u;
+                    accf = fmaf(u, fmaf(fmaf(mixed::kA2, s2, mixed::kA1), s2, mixed::kA0), accf);
                 } else {
                     const float n1 = nn * (1.0f / kNScale);
                     const float ang = atan2f(n1, dd);

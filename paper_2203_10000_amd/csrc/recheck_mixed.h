@@ -16,11 +16,13 @@ namespace sal {
 namespace mixed {
 
 constexpr float kPiF = 3.14159265358979323846f;
-// atan(t) = t16 (1/16 - t16^2 / (3 16^3) + t16^4 / (5 16^5)) for t16 = 16 t,
-// |t| <= 1/16 (the pair loop's small-angle series).
-constexpr float kA0 = 0.0625f;
-constexpr float kA1 = -8.1380208333e-05f;
-constexpr float kA2 = 1.9073486328e-07f;
+// atan(t) = u (1/32 - u^2 / (3 32^3) + u^4 / (5 32^5)) for u = 32 t,
+// |t| <= 1/32: the pair loop's small-angle range, with one more term of the
+// series (first omitted term below 1e-10 t).
+constexpr float kA0 = 0.03125f;
+constexpr float kA1 = -1.0172526042e-05f;   // -1 / (3 * 32768)
+constexpr float kA2 = 5.9604644775e-09f;    //  1 / (5 * 33554432)
+static_assert(kNScale == 32.0f, "series constants assume normals scaled by 32");
 
 struct F64Term {
     double half;      // atan2(N, D)
@@ -69,14 +71,14 @@ __device__ __forceinline__ double strip_sum(const Rec32 *__restrict__ rec32,
         const float cr = __builtin_amdgcn_sqrtf(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
         const float e02 = fmaf(ax, cx, fmaf(ay, cy, az * cz));
         const float e12 = fmaf(bx, cx, fmaf(by, cy, bz * cz));
-        const float nn = fmaf(cx, q[3], fmaf(cy, q[4], cz * q[5]));   // 16 N
+        const float nn = fmaf(cx, q[3], fmaf(cy, q[4], cz * q[5]));   // 32 N
         const float mm = rr01 * cr;
         const float dd = fmaf(e12, ar, fmaf(e02, br, fmaf(e01, cr, mm)));
         const float lim = fmaf(q[7], cr, fmaf(kap, mm, fabsf(nn)));
         if (dd > lim) {
-            const float t16 = nn * __builtin_amdgcn_rcpf(dd);
-            const float s = t16 * t16;
-            accf = fmaf(t16, fmaf(fmaf(kA2, s, kA1), s, kA0), accf);
+            const float u = nn * __builtin_amdgcn_rcpf(dd);
+            const float s = u * u;
+            accf = fmaf(u, fmaf(fmaf(kA2, s, kA1), s, kA0), accf);
         } else {
             const float n1 = nn * (1.0f / kNScale);
             const float ang = atan2f(n1, dd);

@@ -22,11 +22,11 @@ namespace sal {
 // float32 stream, 32 bytes per record, read by every lane of a wavefront at
 // the same address (scalar loads, broadcast through SGPRs):
 //   head: { x0, y0, z0, x1, y1, z1, bits(m), 0 }
-//   tri : { x, y, z,  16 nx, 16 ny, 16 nz,  |n|,  KN_SMALL |n| }
+//   tri : { x, y, z,  32 nx, 32 ny, 32 nz,  |n|,  KN_SMALL |n| }
 // where (x, y, z) is the strip's next vertex and n = (B - A) x (C - A) is the
 // outward (unnormalised) normal of the original triangle (A, B, C), computed in
-// double from the float32 vertices and rounded once.  The factor 16 is a power
-// of two (exact) that folds the small-angle bound |N/D| < 1/16 into one
+// double from the float32 vertices and rounded once.  The factor 32 is a power
+// of two (exact) that folds the small-angle bound |N/D| < 1/32 into one
 // comparison.
 struct alignas(32) Rec32 {
     float v[8];
@@ -41,7 +41,7 @@ struct alignas(64) Rec64 {
     double v[8];
 };
 
-constexpr float kNScale = 16.0f;     // normal pre-scale in the float32 stream
+constexpr float kNScale = 32.0f;     // normal pre-scale in the float32 stream (a power of two)
 constexpr float kKnSmall = 5.0f;     // small-angle path needs D > 5 |n| r_Z + ...
 constexpr int kMaxSurfaces = 64;     // per-point masks are 64-bit
 
