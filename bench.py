@@ -39,7 +39,7 @@ def parse():
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2 (default, the benchmark line); c3 refine-and-relabel, c4 batched, "
-                         "c5 precision stress: measurement lines for the design notes")
+                         "c5 precision stress: recheck fraction and oracle mismatches")
     ap.add_argument("--rule", default="centroid", choices=["centroid", "four_nodes"],
                     help="element rule of the c3 refine-and-relabel run")
     ap.add_argument("--conform", action="store_true",
@@ -451,8 +451,9 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(labeling shards by points; see the design notes).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(labeling would shard by points, one slab of lattice cells per GPU).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -38,7 +38,7 @@ sal_status dev_alloc(T **p, int64_t n) {
     return SAL_OK;
 }
 
-// Frees its buffers when the build ends.
+// Frees its buffers when the graph construction ends.
 struct Temp {
     std::vector<void *> p;
     ~Temp() {
