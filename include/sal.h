@@ -364,7 +364,8 @@ typedef struct sal_smooth_info {
  * all edges.  Nodes on a face of the lattice box never move.  A phase stops
  * after the first iteration k with ||x(k+1/2) - x(k)|| / ||x(0)|| <= xi
  * (norms over the nodes it moves, x(0) their positions at the phase start)
- * or after its iteration cap.  Positions are kept in float32 and each half
+ * or after its iteration cap; a phase with no node to move runs no
+ * iteration.  Positions are kept in float32 and each half
  * step is computed in double.  The edge graph is built on the first call and
  * kept on the mesh; later calls smooth the current positions again.
  *   params  NULL for the defaults;  info  NULL, or filled
