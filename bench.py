@@ -505,6 +505,8 @@ def main():
     fp64 = None
     if args.fp64_steps > 0:
         lab64 = torch.empty_like(labels)
+        for _ in range(max(args.warmup, 1)):      # untimed: the tuner's trials run here
+            sal.label_points(ctx, ss, cen, precision="fp64", out=lab64)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.fp64_steps):
