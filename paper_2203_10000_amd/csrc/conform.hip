@@ -73,13 +73,35 @@ __device__ __forceinline__ bool set_insert(unsigned long long *tkeys, int64_t ca
     return false;
 }
 
+// Sets the bit of every level-0 cell whose closure holds the finest-grid
+// point f (up to 8 cells for a point on cell corners).
+__device__ __forceinline__ void mark_cells(uint32_t *__restrict__ bits, const LatticeGeom &g,
+                                           const int64_t f[3]) {
+    int64_t lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        const int64_t c = f[a] >> kMaxLevels, last = g.cells[a] - 1;
+        const bool on_face = (f[a] & ((1 << kMaxLevels) - 1)) == 0;
+        hi[a] = c < last ? c : last;
+        lo[a] = on_face && c > 0 ? c - 1 : c;
+        if (lo[a] > last) lo[a] = last;
+    }
+    for (int64_t z = lo[2]; z <= hi[2]; ++z)
+        for (int64_t y = lo[1]; y <= hi[1]; ++y)
+            for (int64_t x = lo[0]; x <= hi[0]; ++x) {
+                const int64_t cell = (z * g.cells[1] + y) * g.cells[0] + x;
+                atomicOr(&bits[cell >> 5], 1u << (cell & 31));
+            }
+}
+
 // Inserts the vertices of entries [first, first + count) of level l (leaves
 // or not: an inner entry's vertices are those of its corner children).  Keys
 // that were not in the set are counted in *n_new and, when `fresh` is given,
-// also put in that second set (the vertices new in this closure round).
+// also put in that second set (the vertices new in this closure round), with
+// the bits of the level-0 cells they touch set in `cells_new`.
 __global__ void k_insert_range(LevelPtrs L, LatticeGeom g, int l, int64_t first, int64_t count,
                                unsigned long long *__restrict__ set, int64_t cap,
                                unsigned long long *__restrict__ fresh, int64_t fcap,
+                               uint32_t *__restrict__ cells_new,
                                unsigned long long *__restrict__ n_new,
                                unsigned long long *__restrict__ overflow) {
     const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -89,7 +111,12 @@ __global__ void k_insert_range(LevelPtrs L, LatticeGeom g, int l, int64_t first,
         leaf_fine_vertices(L, g, l, first + (jj >> 2), F);
         const uint64_t key = fine_key(F[jj & 3]);
         if (set_insert(set, cap, key, &added)) {
-            if (added && fresh && !set_insert(fresh, fcap, key, nullptr)) atomicAdd(overflow, 1ull);
+            if (added && fresh) {
+                if (set_insert(fresh, fcap, key, nullptr))
+                    mark_cells(cells_new, g, F[jj & 3]);
+                else
+                    atomicAdd(overflow, 1ull);
+            }
         } else {
             atomicAdd(overflow, 1ull);
         }
@@ -165,9 +192,12 @@ __global__ void k_pattern_full(LevelPtrs L, LatticeGeom g, int l, int64_t first,
 // Update of entries [0, count) of level l after a closure round: the vertex
 // set only grows, so a leaf's new pattern is its old one plus what the
 // vertices added in this round (the `fresh` set) hit.  Entries split in the
-// round are inner now and lose their flag.
+// round are inner now and lose their flag.  Every point a leaf tests lies in
+// the closure of its level-0 cell, so a leaf whose cell got no new vertex
+// keeps its pattern without probing the set.
 __global__ void k_pattern_fresh(LevelPtrs L, LatticeGeom g, int l, int64_t count,
-                                const unsigned long long *__restrict__ fresh, int64_t fcap) {
+                                const unsigned long long *__restrict__ fresh, int64_t fcap,
+                                const uint32_t *__restrict__ cells_new) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const uint8_t old = L.flag[l][i];
@@ -175,6 +205,16 @@ __global__ void k_pattern_fresh(LevelPtrs L, LatticeGeom g, int l, int64_t count
         if (old) L.flag[l][i] = 0;
         return;
     }
+    int64_t cell;
+    if (l == 0) {
+        cell = i / 6;
+    } else {
+        int lk, q;
+        int64_t c[3];
+        split_key(L.key[l][i], lk, q, c);
+        cell = ((c[2] >> l) * g.cells[1] + (c[1] >> l)) * g.cells[0] + (c[0] >> l);
+    }
+    if (!((cells_new[cell >> 5] >> (cell & 31)) & 1u)) return;
     int64_t F[4][3];
     leaf_fine_vertices(L, g, l, i, F);
     const unsigned f = old | leaf_hits(F, l, fresh, fcap);
@@ -330,11 +370,12 @@ inline unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_insert_range(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t first,
                                int64_t count, unsigned long long *set, int64_t cap,
-                               unsigned long long *fresh, int64_t fcap, unsigned long long *n_new,
-                               unsigned long long *overflow, hipStream_t s) {
+                               unsigned long long *fresh, int64_t fcap, uint32_t *cells_new,
+                               unsigned long long *n_new, unsigned long long *overflow,
+                               hipStream_t s) {
     if (count <= 0) return hipSuccess;
     k_insert_range<<<grid_of(4 * count), 256, 0, s>>>(L, g, l, first, count, set, cap, fresh, fcap,
-                                                      n_new, overflow);
+                                                      cells_new, n_new, overflow);
     return hipGetLastError();
 }
 
@@ -347,9 +388,10 @@ hipError_t launch_pattern_full(const LevelPtrs &L, const LatticeGeom &g, int l, 
 }
 
 hipError_t launch_pattern_fresh(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t count,
-                                const unsigned long long *fresh, int64_t fcap, hipStream_t s) {
+                                const unsigned long long *fresh, int64_t fcap,
+                                const uint32_t *cells_new, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    k_pattern_fresh<<<grid_of(count), 256, 0, s>>>(L, g, l, count, fresh, fcap);
+    k_pattern_fresh<<<grid_of(count), 256, 0, s>>>(L, g, l, count, fresh, fcap, cells_new);
     return hipGetLastError();
 }
 

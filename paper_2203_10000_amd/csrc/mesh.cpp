@@ -871,7 +871,7 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
                 LevelPtrs L = ptrs(m);
                 for (int l = 0; l <= m->max_level; ++l)
                     SAL_HIP(launch_insert_range(L, m->g, l, 0, m->n[l], set, cap, nullptr, 0,
-                                                counters, counters + 1, s));
+                                                nullptr, counters, counters + 1, s));
                 unsigned long long c[2] = {0, 0};
                 SAL_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, s));
                 SAL_HIP(hipStreamSynchronize(s));
@@ -888,6 +888,9 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
         int rounds = 0;
         GrowBuf<int32_t> red_buf;              // red leaves of a round
         GrowBuf<unsigned long long> fresh_buf; // vertices new in a round
+        GrowBuf<uint32_t> cells_buf;           // level-0 cells those vertices touch, one bit each
+        const int64_t cell_words =
+            ((int64_t)m->g.cells[0] * m->g.cells[1] * m->g.cells[2] + 31) / 32;
         for (;;) {
             int64_t off[kMaxLevels + 2] = {0};
             for (int l = 0; l <= m->max_level; ++l) off[l + 1] = off[l] + m->n[l];
@@ -929,12 +932,15 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
             while (fcap < 12 * total_red) fcap <<= 1;
             if ((st = fresh_buf.need(fcap)) != SAL_OK) return st;
             unsigned long long *fresh = fresh_buf.p;
+            if ((st = cells_buf.need(cell_words)) != SAL_OK) return st;
+            uint32_t *cells_new = cells_buf.p;
             SAL_HIP(launch_fill_u64(fresh, ~0ull, fcap, s));
+            SAL_HIP(launch_fill_i32((int32_t *)cells_new, 0, cell_words, s));
             SAL_HIP(launch_fill_u64(counters, 0ull, 2, s));
             LevelPtrs L = ptrs(m);
             for (int l = 0; l <= m->max_level; ++l)
                 SAL_HIP(launch_insert_range(L, m->g, l, old_n[l], m->n[l] - old_n[l], set, cap, fresh,
-                                            fcap, counters, counters + 1, s));
+                                            fcap, cells_new, counters, counters + 1, s));
             unsigned long long c[2] = {0, 0};
             SAL_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, s));
             SAL_HIP(hipStreamSynchronize(s));
@@ -950,7 +956,7 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
             // old entries: patterns plus what the new vertices hit; new
             // children: full patterns
             for (int l = 0; l <= m->max_level; ++l) {
-                SAL_HIP(launch_pattern_fresh(L, m->g, l, old_n[l], fresh, fcap, s));
+                SAL_HIP(launch_pattern_fresh(L, m->g, l, old_n[l], fresh, fcap, cells_new, s));
                 SAL_HIP(launch_pattern_full(L, m->g, l, old_n[l], m->n[l] - old_n[l], set, cap, s));
             }
             SAL_HIP(hipStreamSynchronize(s));

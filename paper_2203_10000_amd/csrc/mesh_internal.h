@@ -127,15 +127,19 @@ hipError_t launch_child_masks(const LevelPtrs &L, const LatticeGeom &g, int l,
 // Conforming transition refinement (conform.hip).
 // Flags of a leaf during the closure (in LevelPtrs::flag): bits 0-5 the
 // hanging edges, bit 6 a node at a quarter point, bit 7 split 1 -> 8.
+// cells_new: one bit per level-0 cell, set for the cells a vertex added to
+// `fresh` touches (unused when fresh is null).
 hipError_t launch_insert_range(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t first,
                                int64_t count, unsigned long long *set, int64_t cap,
-                               unsigned long long *fresh, int64_t fcap, unsigned long long *n_new,
-                               unsigned long long *overflow, hipStream_t s);
+                               unsigned long long *fresh, int64_t fcap, uint32_t *cells_new,
+                               unsigned long long *n_new, unsigned long long *overflow,
+                               hipStream_t s);
 hipError_t launch_pattern_full(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t first,
                                int64_t count, const unsigned long long *set, int64_t cap,
                                hipStream_t s);
 hipError_t launch_pattern_fresh(const LevelPtrs &L, const LatticeGeom &g, int l, int64_t count,
-                                const unsigned long long *fresh, int64_t fcap, hipStream_t s);
+                                const unsigned long long *fresh, int64_t fcap,
+                                const uint32_t *cells_new, hipStream_t s);
 hipError_t launch_tet_counts(const LevelPtrs &L, int l, const int32_t *list, int64_t count,
                              int32_t *counts, hipStream_t s);
 // hipCUB device-wide primitives: with tmp == nullptr they only set *tmp_bytes.
