@@ -59,13 +59,18 @@ __device__ __forceinline__ bool set_find(const unsigned long long *tkeys, int64_
 }
 
 // Inserts key; *added tells whether it was new.  False when the table is full.
+// A slot only ever changes from empty to a key, so a key read with a plain
+// load is final: most inserts find their key already there (a vertex is
+// shared by many leaves) and need no atomic; an empty slot is claimed with a
+// compare-and-swap.
 __device__ __forceinline__ bool set_insert(unsigned long long *tkeys, int64_t cap, uint64_t key,
                                            bool *added) {
     uint64_t h = set_hash(key) & (uint64_t)(cap - 1);
     for (int64_t probe = 0; probe < cap; ++probe) {
-        const unsigned long long prev = atomicCAS(&tkeys[h], kEmpty, key);
-        if (prev == kEmpty || prev == key) {
-            if (added) *added = prev == kEmpty;
+        unsigned long long cur = __atomic_load_n(&tkeys[h], __ATOMIC_RELAXED);
+        if (cur == kEmpty) cur = atomicCAS(&tkeys[h], kEmpty, key);
+        if (cur == kEmpty || cur == key) {
+            if (added) *added = cur == kEmpty;
             return true;
         }
         h = (h + 1) & (uint64_t)(cap - 1);
