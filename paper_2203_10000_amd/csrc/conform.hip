@@ -226,12 +226,21 @@ __global__ void k_pattern_fresh(LevelPtrs L, LatticeGeom g, int l, int64_t count
     if (f != old) L.flag[l][i] = with_red(f);
 }
 
-// Tetrahedra per listed leaf: one plus its number of hanging edges.
+// Tetrahedra per listed leaf: one plus its number of hanging edges; hist[k]
+// counts the leaves cut into k + 1 pieces (one atomic per block and bin).
 __global__ void k_tet_counts(LevelPtrs L, int l, const int32_t *__restrict__ list, int64_t count,
-                             int32_t *__restrict__ counts) {
+                             int32_t *__restrict__ counts, unsigned long long *__restrict__ hist) {
+    __shared__ unsigned int bins[4];
+    if (threadIdx.x < 4) bins[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= count) return;
-    counts[j] = 1 + __popc((unsigned)L.flag[l][list[j]] & 63u);
+    if (j < count) {
+        const int c = 1 + __popc((unsigned)L.flag[l][list[j]] & 63u);
+        counts[j] = c;
+        atomicAdd(&bins[(c < 4 ? c : 4) - 1], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && bins[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)bins[threadIdx.x]);
 }
 
 __device__ __forceinline__ void put_tet(int64_t *__restrict__ out, int64_t slot, const int64_t a[3],
@@ -401,9 +410,9 @@ hipError_t launch_pattern_fresh(const LevelPtrs &L, const LatticeGeom &g, int l,
 }
 
 hipError_t launch_tet_counts(const LevelPtrs &L, int l, const int32_t *list, int64_t count,
-                             int32_t *counts, hipStream_t s) {
+                             int32_t *counts, unsigned long long *hist, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    k_tet_counts<<<grid_of(count), 256, 0, s>>>(L, l, list, count, counts);
+    k_tet_counts<<<grid_of(count), 256, 0, s>>>(L, l, list, count, counts, hist);
     return hipGetLastError();
 }
 

@@ -981,11 +981,14 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
         int64_t *offsets = nullptr;
         if ((st = keep.get(&counts, n_all)) != SAL_OK || (st = keep.get(&offsets, n_all)) != SAL_OK)
             return st;
+        unsigned long long *hist = nullptr;   // leaves by number of pieces
+        if ((st = keep.get(&hist, 4)) != SAL_OK) return st;
+        SAL_HIP(launch_fill_u64(hist, 0ull, 4, s));
         {
             LevelPtrs L = ptrs(m);
             int64_t coff = 0;
             for (int l = 0; l <= m->max_level; coff += count[l], ++l)
-                SAL_HIP(launch_tet_counts(L, l, m->list + off[l], count[l], counts + coff, s));
+                SAL_HIP(launch_tet_counts(L, l, m->list + off[l], count[l], counts + coff, hist, s));
         }
         size_t tmp_bytes = 0;
         SAL_HIP(exclusive_sum_i32(counts, offsets, n_all, nullptr, &tmp_bytes, s));
@@ -1038,8 +1041,8 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
         SAL_HIP(hipMemcpyAsync(m->conf_keys, nodes, (size_t)n_nodes * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
         SAL_HIP(launch_node_ids(tkeys, n_corner, m->conf_keys, n_nodes, m->conf_ids, s));
         SAL_HIP(launch_node_xyz(m->g, m->conf_keys, n_nodes, m->conf_xyz, s));
-        std::vector<int32_t> hc((size_t)n_all);
-        SAL_HIP(hipMemcpyAsync(hc.data(), counts, (size_t)n_all * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        unsigned long long hh[4] = {0, 0, 0, 0};
+        SAL_HIP(hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, s));
         SAL_HIP(hipStreamSynchronize(s));
         m->conf_tets = n_tets;
         m->conf_nodes = n_nodes;
@@ -1050,7 +1053,7 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
             info->n_tets = n_tets;
             info->n_nodes = n_nodes;
             info->n_leaves = n_all;
-            for (int32_t c : hc) info->n_by_pieces[std::min(std::max(c, 1), 4) - 1] += 1;
+            for (int k = 0; k < 4; ++k) info->n_by_pieces[k] = (int64_t)hh[k];
             info->closure_rounds = rounds;
         }
         return SAL_OK;
