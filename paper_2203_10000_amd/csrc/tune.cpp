@@ -1,7 +1,8 @@
 // Launch-shape tuner for the pair loop: points per lane x wavefronts per
 // workgroup, timed on the device the first time a (device, precision,
 // triangle-count bucket, point-count bucket) is seen, then cached for the
-// process (and in the file named by SAL_TUNE_CACHE, if set).
+// process (and in the file named by SAL_TUNE_CACHE, if set).  Point counts
+// at or above the trial size share one bucket.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -21,6 +22,8 @@ using Key = std::tuple<int, int, int, int, std::string, int, int>;
 std::mutex g_mu;
 std::map<Key, std::pair<int, int>> g_cache;
 bool g_loaded = false;
+
+constexpr int64_t kTrialPoints = (int64_t)1 << 19;   // enough workgroups to fill the device
 
 int bucket(int64_t v) {
     int b = 0;
@@ -78,7 +81,10 @@ sal_status tune_launch(sal_context *ctx, const sal_surface_set *set, int64_t n, 
         if (opt->block_waves == 0) opt->block_waves = 4;
         return SAL_OK;
     }
-    const Key key(ctx->device, opt->precision, bucket(set->n_tri), bucket(n), arch_name(ctx->device),
+    // The trials use at most kTrialPoints points, so every larger count runs
+    // the same trials: those counts share one entry.
+    const Key key(ctx->device, opt->precision, bucket(set->n_tri),
+                  bucket(n < kTrialPoints ? n : kTrialPoints), arch_name(ctx->device),
                   opt->points_per_lane, opt->block_waves);
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -93,7 +99,7 @@ sal_status tune_launch(sal_context *ctx, const sal_surface_set *set, int64_t n, 
     // Trial launches of the pair loop alone on a prefix of the points (enough
     // workgroups to fill the device several times) against the tuner's strip
     // prefix, writing labels that the real launch overwrites.
-    const int64_t trial_n = n < ((int64_t)1 << 19) ? n : ((int64_t)1 << 19);
+    const int64_t trial_n = n < kTrialPoints ? n : kTrialPoints;
     PairloopArgs a{};
     a.rec32 = set->rec32;
     a.rec64 = set->rec64;
