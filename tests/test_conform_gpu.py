@@ -45,7 +45,18 @@ CASES = {
     "head_centroid": ("head", 8, 2, 2, "centroid"),
     "sphere_three_rounds": ("sphere", 6, 2, 3, "centroid"),
     "head_four_nodes": ("head", 8, 2, 2, "four_nodes"),
+    # a different cell count on each axis, the box cutting through the sphere:
+    # any mix-up of the axes in cell numbering changes the mesh
+    "sphere_uneven_box": ("sphere", (8, 7, 6), 2, 3, "centroid"),
 }
+
+
+def _config(kind, cells, subdiv):
+    if isinstance(cells, tuple):
+        surfaces = synth.config_small(kind, cells=4, subdiv=subdiv).surfaces
+        lat = synth.Lattice(origin=(-100.0, -90.0, -75.0), h=25.0, cells=cells)
+        return synth.Config("uneven-" + kind, surfaces, lattice=lat, precision="fp32")
+    return synth.config_small(kind, cells=cells, subdiv=subdiv)
 
 
 def _oracle_leaves(cfg, rounds, rule):
@@ -62,7 +73,7 @@ def _oracle_leaves(cfg, rounds, rule):
 @pytest.mark.parametrize("case", list(CASES))
 def test_conforming_mesh_equals_the_oracle(ctx, case):
     kind, cells, subdiv, rounds, rule = CASES[case]
-    cfg = synth.config_small(kind, cells=cells, subdiv=subdiv)
+    cfg = _config(kind, cells, subdiv)
     leaves = _oracle_leaves(cfg, rounds, rule)
     want_t, want_l, want_rounds = conform.conforming_mesh(leaves.keys, leaves.labels,
                                                           cfg.lattice.cells)
