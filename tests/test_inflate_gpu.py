@@ -135,3 +135,28 @@ def test_mesh_without_an_interface(ctx):
     info = mesh.inflate(ss, 0.05)
     assert info["n_candidates"] == 0 and info["n_moved"] == 0
     assert np.array_equal(mesh.export_conforming()["xyz"].cpu().numpy().astype(np.float64), got)
+
+
+def test_inflation_on_a_lattice_with_uneven_axes(ctx):
+    """Different cell counts per axis, the box cutting through the sphere: the
+    triangle bins and the box test are numbered per axis, so a mix-up of the
+    axes changes the moved positions."""
+    surfaces = synth.config_small("sphere", cells=4, subdiv=2).surfaces
+    lat = synth.Lattice(origin=(-100.0, -90.0, -75.0), h=25.0, cells=(8, 7, 6))
+    cfg = synth.Config("uneven-sphere", surfaces, lattice=lat, precision="fp32")
+    nodes, ids, lab, xyz0 = _oracle_mesh(cfg, 2)
+    e, surf = smooth.edges(ids, lab)
+    mv = np.zeros(len(nodes), bool)
+    mv[e[surf].reshape(-1)] = True
+    mv &= ~smooth.on_box(nodes, lat.cells)
+    want, chosen, _ = inflate.inflate(xyz0.astype(np.float64), e, mv, nodes,
+                                      inflate.triangles(surfaces), 0.05)
+    mesh, ss = _device(ctx, cfg, 2)
+    info = mesh.inflate(ss, 0.05)
+    out = mesh.export_conforming()
+    assert np.array_equal(out["node_keys"].cpu().numpy(), nodes)
+    assert info["n_candidates"] == mv.sum() and info["n_moved"] == np.sum(chosen >= 0)
+    assert info["n_moved"] > 0
+    got = out["xyz"].cpu().numpy()
+    bad = np.nonzero(np.any(got != want.astype(np.float32), axis=1))[0]
+    assert len(bad) == 0, (len(bad), bad[:5])
