@@ -129,3 +129,24 @@ def test_smoothing_needs_a_conforming_mesh_and_valid_steps(ctx):
             mesh.smooth(**bad)
     info = mesh.smooth(max_iter_surface=0, max_iter_volume=0)
     assert info["iters_surface"] == 0 and info["iters_volume"] == 0
+
+
+def test_smoothing_on_a_lattice_with_uneven_axes(ctx):
+    """Different cell counts per axis, the box cutting through the sphere: the
+    box nodes that never move and the node numbering are per axis."""
+    surfaces = synth.config_small("sphere", cells=4, subdiv=2).surfaces
+    lat = synth.Lattice(origin=(-100.0, -90.0, -75.0), h=25.0, cells=(8, 7, 6))
+    cfg = synth.Config("uneven-sphere", surfaces, lattice=lat, precision="fp32")
+    nodes, ids, lab, xyz0 = _oracle_mesh(cfg, 2)
+    box = smooth.on_box(nodes, lat.cells)
+    kw = dict(xi_surface=-1.0, xi_volume=-1.0, max_iter_surface=2, max_iter_volume=2)
+    want, winfo = smooth.smooth_mesh(ids, lab, xyz0.astype(np.float64), box, **kw)
+    mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    mesh.refine_relabel(sal.SurfaceSet(ctx, surfaces), 2)
+    mesh.conform()
+    info = mesh.smooth(**kw)
+    got = mesh.export_conforming()["xyz"].cpu().numpy().astype(np.float64)
+    for k in ("n_edges", "n_surface_edges", "n_surface_nodes", "n_volume_nodes"):
+        assert info[k] == winfo[k], k
+    assert np.array_equal(got[box], xyz0[box].astype(np.float64))
+    assert np.abs(got - want).max() <= _bound(want, 8)
