@@ -166,8 +166,9 @@ typedef struct sal_label_options {
                                  outside the bounding box of a surface's vertices
                                  (outside its convex hull: w = 0 exactly), or all
                                  inside a ball that the surface does not cross
-                                 (w = that of the ball's centre, 0 or 1, found at
-                                 surface-set creation by the plain FP64 form),
+                                 (w = that of the ball's centre, 0 or 1, found by
+                                 the plain FP64 form on the set's first culling
+                                 call),
                                  skips that surface; the labels are the same.
                                  Default 0.  sal_label_batch ignores it */
     int32_t reserved;
