@@ -138,7 +138,7 @@ int oracle_orient2d_sign(const float a[3], const float b[3], const float c[3], i
 
 /* Sign of det[v0-p, v1-p, v2-p]: the double value when its static error
  * bound certifies the sign, the exact expansion otherwise. */
-static int orient3d_filtered(const float p[3], const float v0[3], const float v1[3],
+int oracle_orient3d(const float p[3], const float v0[3], const float v1[3],
                              const float v2[3])
 {
     double a[3], b[3], c[3];
@@ -255,7 +255,7 @@ static double winding_one(const float p[3], const float *verts, int64_t n_tri,
 
 /* ------------------------------------------------------------ thread pool */
 
-typedef void (*range_fn)(void *ctx, int64_t begin, int64_t end);
+typedef oracle_range_fn range_fn;
 
 struct range_job {
     range_fn fn;
@@ -284,9 +284,10 @@ static int resolve_threads(int n_threads)
     return c > 0 ? (int)c : 1;
 }
 
-/* Splits [0, n) into blocks of at most 64 points handed out round-robin in
- * contiguous chunks per thread; results do not depend on the thread count. */
-static void parallel_for(int64_t n, int n_threads, range_fn fn, void *ctx)
+/* Splits [0, n) into one contiguous range per thread (the last ranges take
+ * the remainder); each index is computed by exactly one thread, so results do
+ * not depend on the thread count. */
+void oracle_parallel_for(int64_t n, int n_threads, range_fn fn, void *ctx)
 {
     int nt = resolve_threads(n_threads);
     if (nt > 256)
@@ -338,7 +339,7 @@ void oracle_winding(int64_t n, const float *px, const float *py, const float *pz
 {
     (void)n_vert;
     struct winding_ctx c = {px, py, pz, verts, tris, n_tri, w, on_surf};
-    parallel_for(n, n_threads, winding_range, &c);
+    oracle_parallel_for(n, n_threads, winding_range, &c);
 }
 
 struct label_ctx {
@@ -390,7 +391,7 @@ int64_t oracle_label(int64_t n, const float *px, const float *py, const float *p
 {
     struct label_ctx c = {px, py, pz, verts, tris, surf_label, vert_off, tri_off,
                           n_surf, n, threshold, labels, w_out, NULL};
-    parallel_for(n, n_threads, label_range, &c);
+    oracle_parallel_for(n, n_threads, label_range, &c);
     return n * (tri_off[n_surf] - tri_off[0]);
 }
 
@@ -403,7 +404,7 @@ int64_t oracle_enclosure(int64_t n, const float *px, const float *py, const floa
                           n_surf, n, threshold, NULL, NULL, masks};
     if (n_surf > 64)
         return -1;
-    parallel_for(n, n_threads, label_range, &c);
+    oracle_parallel_for(n, n_threads, label_range, &c);
     return n * (tri_off[n_surf] - tri_off[0]);
 }
 
@@ -434,13 +435,13 @@ static void radial_range(void *vctx, int64_t b, int64_t e)
             /* p - c = alpha (v0-c) + beta (v1-c) + gamma (v2-c); p is in the
              * closed cone when all three coefficients are >= 0, i.e. when the
              * three cone-side orientations are >= 0. */
-            if (orient3d_filtered(ctr, v0, v1, p) < 0)
+            if (oracle_orient3d(ctr, v0, v1, p) < 0)
                 continue;
-            if (orient3d_filtered(ctr, v1, v2, p) < 0)
+            if (oracle_orient3d(ctr, v1, v2, p) < 0)
                 continue;
-            if (orient3d_filtered(ctr, v2, v0, p) < 0)
+            if (oracle_orient3d(ctr, v2, v0, p) < 0)
                 continue;
-            int s = orient3d_filtered(p, v0, v1, v2);
+            int s = oracle_orient3d(p, v0, v1, v2);
             res = s > 0 ? 1 : (s == 0 ? 2 : 0);
             break;
         }
@@ -453,5 +454,5 @@ void oracle_radial_inside(int64_t n, const float *px, const float *py, const flo
                           const int32_t *tris, int n_threads, uint8_t *out)
 {
     struct radial_ctx c = {px, py, pz, center, verts, tris, n_tri, out};
-    parallel_for(n, n_threads, radial_range, &c);
+    oracle_parallel_for(n, n_threads, radial_range, &c);
 }
