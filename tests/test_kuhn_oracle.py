@@ -227,9 +227,39 @@ def test_node_rule_counts_and_partition():
     assert len(leaves.keys) == n0 + 7 * sum(r["boundary"] for r in st)
     vol = sum(1.0 / 6.0 * 8.0 ** -lv for lv in kuhn.decode(leaves.keys)[0])
     assert abs(vol - np.prod(cfg.lattice.cells)) < 1e-9
-    # every node of every leaf has been labeled exactly once
+    # every node of every leaf has been labeled exactly once: a split keeps
+    # the parent's four vertices among its children's, so the nodes of the
+    # final leaves are every node ever created
     nk = np.unique(kuhn.node_keys(kuhn.vertices_units(leaves.keys)).reshape(-1))
-    assert sum(r["nodes"] for r in st) >= len(nk)
+    assert sum(r["nodes"] for r in st) == len(nk)
+
+
+def test_node_rule_labels_each_node_once_by_brute_force():
+    """Records every point handed to the enclosure test: no node is
+    evaluated twice, and the evaluated nodes are exactly the vertices of the
+    final leaves (found here from the leaves' corners, independently of the
+    oracle's node store)."""
+    cfg = synth.config_small("head", cells=5, subdiv=2)
+    lat = cfg.lattice
+    seen = []
+
+    def mask_fn(p):
+        seen.append(np.asarray(p, dtype=np.float32).T.copy())
+        return oracle.enclosure(p, cfg.surfaces)
+
+    leaves, st = kuhn.refine_relabel_nodes(lat, mask_fn,
+                                           lambda m: oracle.mask_label(m, cfg.surfaces), 2)
+    pts = np.concatenate(seen)
+    assert st[1]["boundary"] > 0 and st[2]["boundary"] > 0
+    assert len(np.unique(pts, axis=0)) == len(pts)          # no node labeled twice
+    corners = set()
+    for key in leaves.keys.tolist():
+        v = kuhn.vertices_units(np.array([key], dtype=np.uint64))[0]     # [4, 3] lattice units
+        for c in v:
+            corners.add(tuple(float(x) for x in c))
+    got = set(tuple(float(x) for x in c) for c in
+              np.round((pts.astype(np.float64) - np.asarray(lat.origin)) / lat.h, 9))
+    assert got == corners
 
 
 @pytest.mark.parametrize("mutant", ["any_node", "three_nodes"])
