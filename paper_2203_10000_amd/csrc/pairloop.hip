@@ -13,7 +13,7 @@
 
 #include "pairloop_f32.h"
 #include "sal_internal.h"
-#include "vos_f64.h"
+#include "pairloop_f64.h"
 
 namespace sal {
 namespace {
@@ -141,7 +141,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     float fx = valid ? a.x[i] : 0.0f, fy = valid ? a.y[i] : 0.0f, fz = valid ? a.z[i] : 0.0f;
     const bool good = valid && finite3(fx, fy, fz);
     if (!good) { fx = 0.0f; fy = 0.0f; fz = 0.0f; }
-    const float praw[3] = {fx, fy, fz};
     const double p[3] = {fx, fy, fz};
     int32_t lab = 0;
     uint64_t enc = 0;
@@ -172,23 +171,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
         }
         if (skip) culled += n_good * (uint64_t)surf[k].n_tri;
-        for (int64_t r = skip ? rec_end : surf[k].rec_begin; r < rec_end;) {
-            double h[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) h[c] = rec[r].v[c];
-            const int m = __double_as_longlong(h[6]) & 0x7fffffff;
-            StripF64 st;
-            f64_strip_head(st, h, p);
-            double acc = 0.0;
-            for (int t = 1; t <= m; ++t) {
-                double q[8];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) q[c] = rec[r + t].v[c];
-                acc += f64_strip_tri(st, q, p, praw, &on, &n_exact);
-            }
-            S += acc;
-            r += m + 1;
-        }
+        else S = f64::surface_sum(rec, surf[k].rec_begin, rec_end, p[0], p[1], p[2], fx, fy, fz, on,
+                                  n_exact);
         const double w = skip ? wfix : S * kInv2Pi;
         if (on || w >= a.threshold) {
             lab = surf[k].label;

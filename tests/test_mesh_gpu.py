@@ -52,9 +52,16 @@ def test_c1_full_lattice_plain_fp64(ctx):
     ss = sal.SurfaceSet(ctx, cfg.surfaces)
     st = mesh.refine_relabel(ss, 0, precision="fp64")
     keys, labels, cen = export_np(mesh)
-    want = oracle.label(kuhn.centroids_mm(keys, lat.origin, lat.h), cfg.surfaces)
+    pts = kuhn.centroids_mm(keys, lat.origin, lat.h)
+    want, w_ref = oracle.label(pts, cfg.surfaces, want_w=True)
     assert np.array_equal(labels, want)
     assert st[0]["n_labeled"] == 196608 and st[0]["n_pairs"] == 196608 * 1280
+    # the FP64 winding number of every centroid, through sal_label_points
+    dev = torch.from_numpy(pts).to("cuda:0").contiguous()
+    lab2, w, _ = sal.label_points(ctx, ss, dev, precision="fp64", winding="f64")
+    torch.cuda.synchronize()
+    assert np.array_equal(lab2.cpu().numpy(), want)
+    assert np.abs(w.cpu().numpy() - w_ref).max() < 1e-12
 
 
 def _refine_case(ctx, precision, cells=16, rounds=2):
