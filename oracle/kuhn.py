@@ -215,33 +215,58 @@ def boundary_mask(leaves, cells, max_level):
     return out
 
 
-def refine_relabel(lattice, label_fn, rounds):
-    """Paper section 2.1.3: label every level-0 centroid, then `rounds` times
-    split each label-boundary leaf into its 8 children and label only the
-    children.  label_fn(points float32 [3, n]) -> int32 labels.
+def _split_marked(leaves, bmask, cells):
+    """Children keys of the marked leaves (grouped by level)."""
+    bkeys = leaves.keys[bmask]
+    if not len(bkeys):
+        return np.zeros(0, dtype=np.uint64)
+    lv = decode(bkeys)[0]
+    return np.concatenate([children(bkeys[lv == x], cells).reshape(-1) for x in np.unique(lv)])
+
+
+def _steps(leaves, cells, rounds, converge, max_steps):
+    """The marking of each recursion step (section 2.1.3 item 2): yields the
+    boundary mask of the current leaves, to be split.  Fixed form: `rounds`
+    steps.  Converging form (Fig. 3: repeat until the boundary between
+    compartments no longer changes): `rounds` is the finest level; every
+    step splits the boundary leaves coarser than it, and the recursion ends
+    with the first step that finds none."""
+    r = 0
+    while converge or r < rounds:
+        top = int(decode(leaves().keys)[0].max())
+        bmask = boundary_mask(leaves(), cells, top)
+        if converge:
+            bmask &= decode(leaves().keys)[0] < rounds
+            if not bmask.any():
+                return
+            if r == max_steps:
+                raise RuntimeError("no convergence within %d steps" % max_steps)
+        r += 1
+        yield bmask
+
+
+def refine_relabel(lattice, label_fn, rounds, converge=False, max_steps=64):
+    """Paper section 2.1.3: label every level-0 centroid, then split each
+    label-boundary leaf into its 8 children and label only the children:
+    `rounds` times, or (converge=True) until no boundary leaf coarser than
+    level `rounds` is left.  label_fn(points float32 [3, n]) -> int32 labels.
 
     Returns (LeafSet, stats) with stats[r] = dict(boundary, children, leaves)."""
     keys = level0_keys(lattice.cells)
     labels = label_fn(centroids_mm(keys, lattice.origin, lattice.h))
-    leaves = LeafSet(keys, labels)
+    state = [LeafSet(keys, labels)]
     stats = [dict(boundary=0, children=0, leaves=len(keys), labeled=len(keys))]
-    for r in range(1, rounds + 1):
-        bmask = boundary_mask(leaves, lattice.cells, r - 1)
-        bkeys = leaves.keys[bmask]
-        if len(bkeys):
-            lv = decode(bkeys)[0]
-            kids = np.concatenate([children(bkeys[lv == x], lattice.cells).reshape(-1)
-                                   for x in np.unique(lv)])
-        else:
-            kids = np.zeros(0, dtype=np.uint64)
+    for bmask in _steps(lambda: state[0], lattice.cells, rounds, converge, max_steps):
+        leaves = state[0]
+        kids = _split_marked(leaves, bmask, lattice.cells)
         klab = label_fn(centroids_mm(kids, lattice.origin, lattice.h)) if len(kids) else \
             np.zeros(0, dtype=np.int32)
         keep = ~bmask
-        leaves = LeafSet(np.concatenate([leaves.keys[keep], kids]),
-                         np.concatenate([leaves.labels[keep], klab]))
+        state[0] = LeafSet(np.concatenate([leaves.keys[keep], kids]),
+                           np.concatenate([leaves.labels[keep], klab]))
         stats.append(dict(boundary=int(bmask.sum()), children=int(len(kids)),
-                          leaves=int(len(leaves.keys)), labeled=int(len(kids))))
-    return leaves, stats
+                          leaves=int(len(state[0].keys)), labeled=int(len(kids))))
+    return state[0], stats
 
 
 # ------------------------------------------------- node-based labeling
@@ -304,13 +329,14 @@ def element_masks(keys, store):
     return m[:, 0] & m[:, 1] & m[:, 2] & m[:, 3]
 
 
-def refine_relabel_nodes(lattice, mask_fn, label_of_mask, rounds):
+def refine_relabel_nodes(lattice, mask_fn, label_of_mask, rounds, converge=False, max_steps=64):
     """Section 2.1.3 read literally: the solid-angle test is applied to the
     nodes (item 1 labels every node of the lattice); a tetrahedron belongs to
     a surface when all four of its nodes are enclosed, and takes the label of
-    the highest-priority such surface (else 0); then, `rounds` times, every
-    label-boundary leaf is split into its 8 children and only nodes not
-    labeled before are evaluated (item 2).
+    the highest-priority such surface (else 0); then every label-boundary
+    leaf is split into its 8 children and only nodes not labeled before are
+    evaluated (item 2): `rounds` times, or (converge=True) until no boundary
+    leaf coarser than level `rounds` is left.
     mask_fn(points float32 [3, n]) -> uint64 enclosure masks;
     label_of_mask(uint64 masks) -> int32 labels.
 
@@ -320,17 +346,11 @@ def refine_relabel_nodes(lattice, mask_fn, label_of_mask, rounds):
     nodes = lattice_nodes_units(lattice.cells)
     store.add(node_keys(nodes), mask_fn(nodes_mm(nodes, lattice.origin, lattice.h)))
     keys = level0_keys(lattice.cells)
-    leaves = LeafSet(keys, label_of_mask(element_masks(keys, store)))
+    state = [LeafSet(keys, label_of_mask(element_masks(keys, store)))]
     stats = [dict(boundary=0, children=0, leaves=len(keys), nodes=len(nodes))]
-    for r in range(1, rounds + 1):
-        bmask = boundary_mask(leaves, lattice.cells, r - 1)
-        bkeys = leaves.keys[bmask]
-        if len(bkeys):
-            lv = decode(bkeys)[0]
-            kids = np.concatenate([children(bkeys[lv == x], lattice.cells).reshape(-1)
-                                   for x in np.unique(lv)])
-        else:
-            kids = np.zeros(0, dtype=np.uint64)
+    for bmask in _steps(lambda: state[0], lattice.cells, rounds, converge, max_steps):
+        leaves = state[0]
+        kids = _split_marked(leaves, bmask, lattice.cells)
         n_new = 0
         if len(kids):
             v = vertices_units(kids).reshape(-1, 3)
@@ -343,8 +363,8 @@ def refine_relabel_nodes(lattice, mask_fn, label_of_mask, rounds):
         else:
             klab = np.zeros(0, dtype=np.int32)
         keep = ~bmask
-        leaves = LeafSet(np.concatenate([leaves.keys[keep], kids]),
-                         np.concatenate([leaves.labels[keep], klab]))
+        state[0] = LeafSet(np.concatenate([leaves.keys[keep], kids]),
+                           np.concatenate([leaves.labels[keep], klab]))
         stats.append(dict(boundary=int(bmask.sum()), children=int(len(kids)),
-                          leaves=int(len(leaves.keys)), nodes=n_new))
-    return leaves, stats
+                          leaves=int(len(state[0].keys)), nodes=n_new))
+    return state[0], stats

@@ -299,10 +299,6 @@ sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_
     sal_label_options opt;
     sal_status st = resolve_options(opt_in, &opt);
     if (st != SAL_OK) return st;
-    if (opt.cull_bounds && n > 0) {
-        SAL_HIP(hipSetDevice(ctx->device));
-        if ((st = ensure_surface_balls(ctx, set)) != SAL_OK) return st;
-    }
     if (winding && opt.winding_type == SAL_WINDING_NONE)
         return set_error(SAL_ERR_INVALID_ARG, "winding buffer given with SAL_WINDING_NONE");
     if (n > 0 && (!x || !y || !z || !labels))
@@ -310,6 +306,8 @@ sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (n == 0) return SAL_OK;
     SAL_HIP(hipSetDevice(ctx->device));
+    // every argument is checked before anything is enqueued
+    if (opt.cull_bounds && (st = ensure_surface_balls(ctx, set)) != SAL_OK) return st;
     if (opt.precision == SAL_PREC_FP32_RECHECK) {
         st = ensure_flag_capacity(ctx, n);
         if (st != SAL_OK) return st;

@@ -479,7 +479,8 @@ sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set
     if (opt.points_per_lane == 0 || opt.block_waves == 0) {
         const int64_t nt = std::min<int64_t>(std::min<int64_t>(m->n[0], kid_cap), (int64_t)1 << 19);
         SAL_HIP(launch_lattice_centroids(m->g, nt, m->cen[0], m->cen[1], m->cen[2], s));
-        if ((st = tune_launch(ctx, set, kid_cap, m->cen[0], m->cen[1], m->cen[2], m->lab_scratch,
+        // the trials read only the nt centroids written here
+        if ((st = tune_launch(ctx, set, nt, m->cen[0], m->cen[1], m->cen[2], m->lab_scratch,
                               &opt)) != SAL_OK)
             return st;
     }

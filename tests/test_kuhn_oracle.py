@@ -129,8 +129,20 @@ def _bruteforce_boundary(ls):
         s = [dot(cross(sub(f[(i + 1) % 3], f[i]), sub(g, f[i])), n) for i in range(3)]
         return all(x > 0 for x in s)
 
+    def plane(f):
+        # the face's plane, scaled so its first nonzero normal component is 1
+        n = cross(sub(f[1], f[0]), sub(f[2], f[0]))
+        lead = next(x for x in n if x != 0)
+        n = tuple(x / lead for x in n)
+        return n + (dot(n, f[0]),)
+
+    # only faces in one plane can touch in 2-D: pair them within each plane
+    by_plane = {}
+    for fc in faces:
+        by_plane.setdefault(plane(fc[1]), []).append(fc)
+    pairs = (pq for group in by_plane.values() for pq in combinations(group, 2))
     flag = np.zeros(len(V), bool)
-    for (ti, f, ot), (ui, g, ou) in combinations(faces, 2):
+    for (ti, f, ot), (ui, g, ou) in pairs:
         if ti == ui or ls.labels[ti] == ls.labels[ui]:
             continue
         n = cross(sub(f[1], f[0]), sub(f[2], f[0]))
@@ -278,3 +290,84 @@ def test_node_pins_catch_a_wrong_element_rule(monkeypatch, mutant):
                                                 "three_nodes": three_nodes}[mutant])
     with pytest.raises(AssertionError):
         test_node_rule_on_a_sphere_matches_the_exact_radial_test()
+
+
+# ------------------------------------------- recursion until convergence
+def _plane_label(p):
+    """A compartment bounded by an oblique plane (label 1 above it)."""
+    p = np.asarray(p, dtype=np.float64)
+    return (p[0] + 0.37 * p[1] + 0.11 * p[2] > 13.0).astype(np.int32)
+
+
+def test_converging_recursion_is_a_fixed_point_by_brute_force():
+    """Fig. 3: the recursion ends when the boundary no longer changes.  With
+    finest level L, the final leaves have no label-boundary leaf coarser than
+    L (checked by exact pairwise face contact); the fixed two-round form on
+    the same input leaves such leaves behind, so the two forms differ."""
+    lat = synth.Lattice(origin=(-100.0, -100.0, -100.0), h=100.0, cells=(2, 2, 1))
+    fixed, _ = kuhn.refine_relabel(lat, _plane_label, 2)
+    conv, st = kuhn.refine_relabel(lat, _plane_label, 2, converge=True)
+    lv_fixed = kuhn.decode(fixed.keys)[0]
+    assert (_bruteforce_boundary(fixed) & (lv_fixed < 2)).any()
+    lv = kuhn.decode(conv.keys)[0]
+    assert lv.max() == 2
+    assert not (_bruteforce_boundary(conv) & (lv < 2)).any()
+    assert len(st) - 1 > 2                      # more steps than levels
+    assert all(s["boundary"] > 0 for s in st[1:])
+    n0 = lat.n_points
+    assert len(conv.keys) == n0 + 7 * sum(s["boundary"] for s in st)
+    vol = np.abs(_vol6(kuhn.vertices_units(conv.keys))).sum() / 6
+    assert vol == pytest.approx(np.prod(lat.cells), abs=1e-12)
+    assert np.array_equal(_plane_label(kuhn.centroids_mm(conv.keys, lat.origin, lat.h)),
+                          conv.labels)
+
+
+def test_converging_recursion_contains_the_fixed_rounds():
+    """Every leaf of the fixed form is a leaf or an ancestor of leaves of the
+    converged form (the converging recursion only adds splits), and with no
+    boundary at all both forms keep the lattice."""
+    cfg = synth.config_small("sphere", cells=6, subdiv=2)
+    lat = cfg.lattice
+    fn = lambda p: oracle.label(p, cfg.surfaces)          # noqa: E731
+    fixed, _ = kuhn.refine_relabel(lat, fn, 2)
+    conv, st = kuhn.refine_relabel(lat, fn, 2, converge=True)
+    assert len(conv.keys) >= len(fixed.keys)
+    # locate an interior point of each converged leaf (generic barycentric
+    # weights, so it lies on no facet of any level) in the fixed mesh: the
+    # containing fixed leaf must be the leaf itself or an ancestor (not finer)
+    wts = np.array([0.4012, 0.2987, 0.1993, 0.1008])
+    inner = np.einsum("k,nkd->nd", wts, kuhn.vertices_units(conv.keys).astype(np.float64))
+    owner = kuhn.containing_leaf(fixed, inner, lat.cells, 2)
+    assert (owner >= 0).all()
+    assert (kuhn.decode(fixed.keys[owner])[0] <= kuhn.decode(conv.keys)[0]).all()
+    empty, st0 = kuhn.refine_relabel(lat, lambda p: np.zeros(p.shape[1], np.int32), 2,
+                                     converge=True)
+    assert len(st0) == 1 and len(empty.keys) == lat.n_points
+
+
+def test_converging_node_rule_labels_each_node_once():
+    """The four-node rule under the converging recursion: no node evaluated
+    twice, the evaluated nodes are the final leaves' vertices, and no
+    boundary leaf coarser than the finest level is left."""
+    cfg = synth.config_small("head", cells=5, subdiv=2)
+    lat = cfg.lattice
+    seen = []
+
+    def mask_fn(p):
+        seen.append(np.asarray(p, dtype=np.float32).T.copy())
+        return oracle.enclosure(p, cfg.surfaces)
+
+    leaves, st = kuhn.refine_relabel_nodes(lat, mask_fn,
+                                           lambda m: oracle.mask_label(m, cfg.surfaces), 2,
+                                           converge=True)
+    pts = np.concatenate(seen)
+    assert len(np.unique(pts, axis=0)) == len(pts)
+    assert sum(s["nodes"] for s in st) == len(pts)
+    lv = kuhn.decode(leaves.keys)[0]
+    assert not (kuhn.boundary_mask(leaves, lat.cells, 2) & (lv < 2)).any()
+    corners = set()
+    for c in kuhn.vertices_units(leaves.keys).reshape(-1, 3):
+        corners.add(tuple(float(x) for x in c))
+    got = set(tuple(float(x) for x in c) for c in
+              np.round((pts.astype(np.float64) - np.asarray(lat.origin)) / lat.h, 9))
+    assert got == corners
