@@ -157,7 +157,8 @@ typedef struct sal_label_options {
                                  surface sets, pointers, sizes, options) come back;
                                  sal_refine_relabel: 1 = run the rounds as launches of
                                  one captured round graph (see there; centroid
-                                 rule only, the four-node rule runs host-driven);
+                                 rule only: with the four-node rule it is
+                                 rejected with SAL_ERR_INVALID_ARG);
                                  sal_label_points ignores it */
     int32_t element_rule;     /* SAL_RULE_* for sal_refine_relabel; fixed by a mesh's
                                  first labeling (a later call with another rule
@@ -275,6 +276,32 @@ typedef struct sal_refine_stats {
 sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *mesh, const sal_surface_set *set,
                               int32_t rounds, const sal_label_options *opt,
                               sal_refine_stats *per_round);
+
+/* Section 2.1.3 item 2 and Fig. 3: the recursion repeated until the
+ * boundary between compartments no longer changes.  Labels every unlabeled
+ * leaf (as sal_refine_relabel's round 0), then repeats steps: mark each leaf
+ * sharing a 2-D part of a face with a leaf of another label, split the
+ * marked leaves that are coarser than `finest_level` 1 -> 8 and label only
+ * the children (or, under the four-node rule, only the new nodes).  The
+ * recursion has converged with the first step that finds no such leaf: then
+ * every leaf on a label boundary is at `finest_level` and another step would
+ * change nothing.  It ends there, or after `max_steps` steps that split.
+ *   finest_level  0..3 (refinement levels above the lattice)
+ *   per_step      NULL, or [max_steps + 1]: entry 0 the lattice labeling,
+ *                 entry s the s-th step that split (filled after
+ *                 synchronising); the final step that splits nothing is
+ *                 not recorded
+ *   n_steps       NULL, or receives the number of steps that split
+ *   converged     NULL, or receives 1 when the recursion converged, 0 when
+ *                 max_steps steps all split
+ * The rounds are host-driven (opt->use_graph must be 0).  The element rule
+ * and the leaves' storage are those of sal_refine_relabel; a mesh may mix
+ * calls of both. */
+sal_status sal_refine_relabel_converge(sal_context *ctx, sal_tet_mesh *mesh,
+                                       const sal_surface_set *set, int32_t finest_level,
+                                       int32_t max_steps, const sal_label_options *opt,
+                                       sal_refine_stats *per_step, int32_t *n_steps,
+                                       int32_t *converged);
 
 /* Number of leaves and the deepest level present. */
 sal_status sal_tet_mesh_size(const sal_tet_mesh *mesh, int64_t *n_leaves, int32_t *max_level);

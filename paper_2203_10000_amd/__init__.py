@@ -150,6 +150,9 @@ _SIGNATURES = [
     ("sal_tet_mesh_destroy", None, [_P]),
     ("sal_refine_relabel", ctypes.c_int,
      [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(LabelOptions), ctypes.POINTER(RefineStats)]),
+    ("sal_refine_relabel_converge", ctypes.c_int,
+     [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(LabelOptions),
+      ctypes.POINTER(RefineStats), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     ("sal_tet_mesh_size", ctypes.c_int,
      [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     ("sal_tet_mesh_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
@@ -345,6 +348,18 @@ class TetMesh:
         _check(lib().sal_refine_relabel(self.ctx.handle, self.handle, sset.handle, int(rounds),
                                         ctypes.byref(o), st))
         return [s.as_dict() for s in st]
+
+    def refine_converge(self, sset, finest_level, max_steps=32, precision="fp32", **opt):
+        """sal_refine_relabel_converge: (per-step stats, converged)."""
+        o = label_options(precision=precision, **opt)
+        st = (RefineStats * (max_steps + 1))()
+        n = ctypes.c_int32()
+        conv = ctypes.c_int32()
+        _check(lib().sal_refine_relabel_converge(self.ctx.handle, self.handle, sset.handle,
+                                                 int(finest_level), int(max_steps),
+                                                 ctypes.byref(o), st, ctypes.byref(n),
+                                                 ctypes.byref(conv)))
+        return [s.as_dict() for s in st[:n.value + 1]], bool(conv.value)
 
     def export(self, keys=True, labels=True, centroids=True):
         import torch

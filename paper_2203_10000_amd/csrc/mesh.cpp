@@ -245,9 +245,12 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 // One host-driven round (section 2.1.3 item 2): mark, compact, then for each
 // level, deepest first, split the marked leaves and label their children.
+// Marked leaves at level `finest` or deeper are left as they are (the
+// converging recursion); without a limit a marked level-3 leaf is an error.
 // Synchronises once to size the new level (and once per level for timing).
 sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
-                       const sal_label_options &opt, sal_refine_stats *out) {
+                       const sal_label_options &opt, sal_refine_stats *out,
+                       int finest = kMaxLevels + 1, int64_t *n_split_out = nullptr) {
     hipStream_t s = ctx->stream;
     sal_status st;
     const int top = m->max_level;
@@ -270,6 +273,7 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
     int64_t count[kMaxLevels + 1] = {0};
     SAL_HIP(hipMemcpyAsync(count, m->totals, sizeof(int64_t) * (top + 1), hipMemcpyDeviceToHost, s));
     SAL_HIP(hipStreamSynchronize(s));
+    for (int l = finest; l <= top; ++l) count[l] = 0;
     if (top == kMaxLevels && count[top] > 0)
         return set_error(SAL_ERR_CAPACITY, "refinement beyond level 3");
     int64_t n_split = 0, n_label = 0;
@@ -350,6 +354,7 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
         }
     }
     m->n_leaves += 7 * n_split;
+    if (n_split_out) *n_split_out = n_split;
     SAL_HIP(hipEventRecord(m->ev[8], s));
     if (out) {
         unsigned long long cnt[kNumCounters];
@@ -735,84 +740,101 @@ sal_status sal_tet_mesh_size(const sal_tet_mesh *m, int64_t *n_leaves, int32_t *
     return SAL_OK;
 }
 
+namespace {
+
+// Arguments shared by the refinement entry points; fills the resolved
+// options.  Nothing is enqueued.
+sal_status check_refine_args(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
+                             const sal_label_options *opt_in, sal_label_options *opt) {
+    if (!ctx || !m || !set) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+    if (set->device != ctx->device || m->device != ctx->device)
+        return set_error(SAL_ERR_INVALID_ARG, "objects live on different devices");
+    sal_status st = resolve_options(opt_in, opt);
+    if (st != SAL_OK) return st;
+    opt->winding_type = SAL_WINDING_NONE;
+    if (m->conformed)
+        return set_error(SAL_ERR_INVALID_ARG, "the mesh was made conforming; it cannot be refined");
+    if (m->labeled0 && m->rule != opt->element_rule)
+        return set_error(SAL_ERR_INVALID_ARG, "the mesh was labeled with another element rule");
+    if (opt->use_graph && opt->element_rule == SAL_RULE_FOUR_NODES)
+        return set_error(SAL_ERR_INVALID_ARG,
+                         "use_graph applies to the centroid rule; the four-node rule runs host-driven");
+    return SAL_OK;
+}
+
+// Section 2.1.3 item 1: labels the whole lattice if it is not labeled yet
+// (the centroids, or under the four-node rule every lattice node and then
+// each tetrahedron from its four nodes).  r0 (if set) gets the round's stats.
+sal_status label_lattice(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
+                         const sal_label_options &opt, sal_refine_stats *r0) {
+    hipStream_t s = ctx->stream;
+    sal_status st;
+    SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, s));
+    SAL_HIP(hipEventRecord(m->ev[0], s));
+    int64_t labeled0 = 0;
+    if (!m->labeled0 && opt.element_rule == SAL_RULE_FOUR_NODES) {
+        m->rule = SAL_RULE_FOUR_NODES;
+        const int64_t n_nodes = (int64_t)(m->g.cells[0] + 1) * (m->g.cells[1] + 1) *
+                                (int64_t)(m->g.cells[2] + 1);
+        if ((st = ensure_centroids(m, n_nodes, s)) != SAL_OK) return st;
+        if ((st = ensure_buf(&m->lab_scratch, &m->lab_cap, n_nodes, s)) != SAL_OK) return st;
+        if (!m->node0 && hipMalloc((void **)&m->node0, (size_t)n_nodes * sizeof(uint64_t)) !=
+                             hipSuccess)
+            return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(node masks)");
+        SAL_HIP(launch_lattice_nodes(m->g, n_nodes, m->cen[0], m->cen[1], m->cen[2], s));
+        if ((st = label_scratch(ctx, m, set, n_nodes, opt, m->lab_scratch, m->ev[10], m->ev[9],
+                                m->node0)) != SAL_OK)
+            return st;
+        SAL_HIP(launch_elem_from_nodes0(m->g, m->n[0], m->node0, set->surf, m->label[0], s));
+        m->labeled0 = true;
+        labeled0 = n_nodes;
+    } else if (!m->labeled0) {
+        m->rule = SAL_RULE_CENTROID;
+        if ((st = ensure_centroids(m, m->n[0], s)) != SAL_OK) return st;
+        SAL_HIP(launch_lattice_centroids(m->g, m->n[0], m->cen[0], m->cen[1], m->cen[2], s));
+        if ((st = label_scratch(ctx, m, set, m->n[0], opt, m->label[0], m->ev[10], m->ev[9])) !=
+            SAL_OK)
+            return st;
+        m->labeled0 = true;
+        labeled0 = m->n[0];
+    } else {
+        SAL_HIP(hipEventRecord(m->ev[10], s));
+        SAL_HIP(hipEventRecord(m->ev[9], s));
+    }
+    SAL_HIP(hipEventRecord(m->ev[1], s));
+    if (r0) {
+        unsigned long long cnt[kNumCounters];
+        SAL_HIP(hipEventSynchronize(m->ev[1]));
+        SAL_HIP(hipMemcpy(cnt, ctx->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+        r0->n_leaves = m->n_leaves;
+        r0->n_labeled = labeled0;
+        r0->n_pairs = labeled0 * set->n_tri;
+        r0->n_recheck_pairs = (int64_t)cnt[kCntRecheck];
+        r0->ms_label = elapsed(m->ev[10], m->ev[9]);
+        r0->ms_recheck = elapsed(m->ev[9], m->ev[1]);
+        r0->ms_total = elapsed(m->ev[0], m->ev[1]);
+    }
+    return SAL_OK;
+}
+
+}  // namespace
+
 sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set *set,
                               int32_t rounds, const sal_label_options *opt_in,
                               sal_refine_stats *per_round) {
     try {
-        if (!ctx || !m || !set) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
-        if (rounds < 0) return set_error(SAL_ERR_INVALID_ARG, "rounds < 0");
-        if (set->device != ctx->device || m->device != ctx->device)
-            return set_error(SAL_ERR_INVALID_ARG, "objects live on different devices");
         sal_label_options opt;
-        sal_status st = resolve_options(opt_in, &opt);
+        sal_status st = check_refine_args(ctx, m, set, opt_in, &opt);
         if (st != SAL_OK) return st;
-        if (opt.cull_bounds) {
-            SAL_HIP(hipSetDevice(ctx->device));
-            if ((st = ensure_surface_balls(ctx, set)) != SAL_OK) return st;
-        }
-        opt.winding_type = SAL_WINDING_NONE;
-        if (m->conformed)
-            return set_error(SAL_ERR_INVALID_ARG, "the mesh was made conforming; it cannot be refined");
+        if (rounds < 0) return set_error(SAL_ERR_INVALID_ARG, "rounds < 0");
         if (m->max_level + rounds > kMaxLevels)
             return set_error(SAL_ERR_CAPACITY, "at most 3 refinement levels");
         SAL_HIP(hipSetDevice(ctx->device));
-        hipStream_t s = ctx->stream;
+        if (opt.cull_bounds && (st = ensure_surface_balls(ctx, set)) != SAL_OK) return st;
         if (per_round) std::memset(per_round, 0, sizeof(sal_refine_stats) * (size_t)(rounds + 1));
-        unsigned long long cnt[kNumCounters];
-
-        // round 0: the whole lattice (paper section 2.1.3 item 1)
-        SAL_HIP(launch_fill_u64(ctx->counters, 0ull, kNumCounters, s));
-        SAL_HIP(hipEventRecord(m->ev[0], s));
-        int64_t labeled0 = 0;
-        if (m->labeled0 && m->rule != opt.element_rule)
-            return set_error(SAL_ERR_INVALID_ARG, "the mesh was labeled with another element rule");
-        if (!m->labeled0 && opt.element_rule == SAL_RULE_FOUR_NODES) {
-            // item 1 read literally: every node of the lattice, then each
-            // tetrahedron from its four nodes
-            m->rule = SAL_RULE_FOUR_NODES;
-            const int64_t n_nodes = (int64_t)(m->g.cells[0] + 1) * (m->g.cells[1] + 1) *
-                                    (int64_t)(m->g.cells[2] + 1);
-            if ((st = ensure_centroids(m, n_nodes, s)) != SAL_OK) return st;
-            if ((st = ensure_buf(&m->lab_scratch, &m->lab_cap, n_nodes, s)) != SAL_OK) return st;
-            if (!m->node0 && hipMalloc((void **)&m->node0, (size_t)n_nodes * sizeof(uint64_t)) !=
-                                 hipSuccess)
-                return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(node masks)");
-            SAL_HIP(launch_lattice_nodes(m->g, n_nodes, m->cen[0], m->cen[1], m->cen[2], s));
-            if ((st = label_scratch(ctx, m, set, n_nodes, opt, m->lab_scratch, m->ev[10],
-                                    m->ev[9], m->node0)) != SAL_OK)
-                return st;
-            SAL_HIP(launch_elem_from_nodes0(m->g, m->n[0], m->node0, set->surf, m->label[0], s));
-            m->labeled0 = true;
-            labeled0 = n_nodes;
-        } else if (!m->labeled0) {
-            m->rule = SAL_RULE_CENTROID;
-            if ((st = ensure_centroids(m, m->n[0], s)) != SAL_OK) return st;
-            SAL_HIP(launch_lattice_centroids(m->g, m->n[0], m->cen[0], m->cen[1], m->cen[2], s));
-            if ((st = label_scratch(ctx, m, set, m->n[0], opt, m->label[0], m->ev[10],
-                                    m->ev[9])) != SAL_OK)
-                return st;
-            m->labeled0 = true;
-            labeled0 = m->n[0];
-        } else {
-            SAL_HIP(hipEventRecord(m->ev[10], s));
-            SAL_HIP(hipEventRecord(m->ev[9], s));
-        }
-        SAL_HIP(hipEventRecord(m->ev[1], s));
-        if (per_round) {
-            SAL_HIP(hipEventSynchronize(m->ev[1]));
-            SAL_HIP(hipMemcpy(cnt, ctx->counters, sizeof(cnt), hipMemcpyDeviceToHost));
-            sal_refine_stats &r0 = per_round[0];
-            r0.n_leaves = m->n_leaves;
-            r0.n_labeled = labeled0;
-            r0.n_pairs = labeled0 * set->n_tri;
-            r0.n_recheck_pairs = (int64_t)cnt[kCntRecheck];
-            r0.ms_label = elapsed(m->ev[10], m->ev[9]);
-            r0.ms_recheck = elapsed(m->ev[9], m->ev[1]);
-            r0.ms_total = elapsed(m->ev[0], m->ev[1]);
-        }
-
+        if ((st = label_lattice(ctx, m, set, opt, per_round)) != SAL_OK) return st;
         int first = 1;
-        if (opt.use_graph && rounds > 0 && m->rule == SAL_RULE_CENTROID) {
+        if (opt.use_graph && rounds > 0) {
             int done = 0;
             st = graph_rounds(ctx, m, set, opt, rounds, per_round ? per_round + 1 : nullptr, &done);
             if (st != SAL_OK) return st;
@@ -824,6 +846,45 @@ sal_status sal_refine_relabel(sal_context *ctx, sal_tet_mesh *m, const sal_surfa
         return SAL_OK;
     } catch (...) {
         return set_error(SAL_ERR_INTERNAL, "exception in sal_refine_relabel");
+    }
+}
+
+sal_status sal_refine_relabel_converge(sal_context *ctx, sal_tet_mesh *m,
+                                       const sal_surface_set *set, int32_t finest_level,
+                                       int32_t max_steps, const sal_label_options *opt_in,
+                                       sal_refine_stats *per_step, int32_t *n_steps,
+                                       int32_t *converged) {
+    try {
+        sal_label_options opt;
+        sal_status st = check_refine_args(ctx, m, set, opt_in, &opt);
+        if (st != SAL_OK) return st;
+        if (finest_level < 0 || finest_level > kMaxLevels)
+            return set_error(SAL_ERR_INVALID_ARG, "finest_level outside 0..3");
+        if (max_steps < 0) return set_error(SAL_ERR_INVALID_ARG, "max_steps < 0");
+        if (opt.use_graph)
+            return set_error(SAL_ERR_INVALID_ARG, "the converging recursion runs host-driven");
+        SAL_HIP(hipSetDevice(ctx->device));
+        if (opt.cull_bounds && (st = ensure_surface_balls(ctx, set)) != SAL_OK) return st;
+        if (per_step) std::memset(per_step, 0, sizeof(sal_refine_stats) * (size_t)(max_steps + 1));
+        if (n_steps) *n_steps = 0;
+        if (converged) *converged = 0;
+        if ((st = label_lattice(ctx, m, set, opt, per_step)) != SAL_OK) return st;
+        for (int step = 1; step <= max_steps; ++step) {
+            sal_refine_stats one{};
+            int64_t split = 0;
+            if ((st = eager_round(ctx, m, set, opt, per_step ? &one : nullptr, finest_level,
+                                  &split)) != SAL_OK)
+                return st;
+            if (split == 0) {
+                if (converged) *converged = 1;
+                return SAL_OK;
+            }
+            if (per_step) per_step[step] = one;
+            if (n_steps) *n_steps = step;
+        }
+        return SAL_OK;
+    } catch (...) {
+        return set_error(SAL_ERR_INTERNAL, "exception in sal_refine_relabel_converge");
     }
 }
 

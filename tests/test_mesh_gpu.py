@@ -177,17 +177,53 @@ def test_four_node_rule_two_rounds(ctx, node_oracle, precision):
         assert st[r]["n_labeled"] == ost[r]["nodes"]   # each new node labeled once
 
 
-def test_four_node_rule_asked_for_a_graph_runs_host_driven(ctx, node_oracle):
-    cfg, leaves, _ = node_oracle
+def test_four_node_rule_rejects_the_round_graph(ctx, node_oracle):
+    """use_graph applies to the centroid rule: with the four-node rule the call
+    fails before anything is labeled."""
+    cfg, _, _ = node_oracle
     lat = cfg.lattice
     mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
     ss = sal.SurfaceSet(ctx, cfg.surfaces)
-    st = mesh.refine_relabel(ss, 2, rule="four_nodes", use_graph=True)
-    assert all(s["graph"] == 0 for s in st)
+    with pytest.raises(sal.SalError) as e:
+        mesh.refine_relabel(ss, 2, rule="four_nodes", use_graph=True)
+    assert e.value.status == 1
+    _, labels, _ = export_np(mesh)
+    assert np.all(labels == -2) and mesh.size() == (lat.n_points, 0)
+
+
+@pytest.mark.parametrize("rule", ["centroid", "four_nodes"])
+def test_converging_recursion_matches_the_oracle(ctx, rule):
+    """Section 2.1.3 item 2 / Fig. 3: steps repeat until no boundary leaf
+    coarser than the finest level is left; leaves, labels and the per-step
+    counts equal the oracle's."""
+    cfg = synth.config_small("head", cells=10, subdiv=3)
+    lat = cfg.lattice
+    if rule == "centroid":
+        want, ost = kuhn.refine_relabel(lat, lambda p: oracle.label(p, cfg.surfaces), 2,
+                                        converge=True)
+    else:
+        want, ost = kuhn.refine_relabel_nodes(lat, lambda p: oracle.enclosure(p, cfg.surfaces),
+                                              lambda m: oracle.mask_label(m, cfg.surfaces), 2,
+                                              converge=True)
+    assert len(ost) - 1 > 2                      # the recursion goes past two steps
+    mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    st, conv = mesh.refine_converge(ss, 2, max_steps=16, rule=rule)
+    assert conv and len(st) == len(ost)
     keys, labels, _ = export_np(mesh)
     order = np.argsort(keys)
-    assert np.array_equal(keys[order], leaves.keys)
-    assert np.array_equal(labels[order], leaves.labels)
+    assert np.array_equal(keys[order], want.keys)
+    assert np.array_equal(labels[order], want.labels)
+    for r in range(1, len(st)):
+        assert st[r]["n_boundary"] == ost[r]["boundary"]
+        assert st[r]["n_leaves"] == ost[r]["leaves"]
+        assert st[r]["n_labeled"] == ost[r]["labeled" if rule == "centroid" else "nodes"]
+    # a second call finds nothing to split; a cap of one step reports no convergence
+    st2, conv2 = mesh.refine_converge(ss, 2, rule=rule)
+    assert conv2 and len(st2) == 1 and mesh.size()[0] == len(want.keys)
+    other = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    st3, conv3 = other.refine_converge(ss, 2, max_steps=1, rule=rule)
+    assert not conv3 and len(st3) == 2
 
 
 def test_element_rule_is_fixed_by_the_first_labeling(ctx):
