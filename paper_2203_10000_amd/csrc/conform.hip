@@ -10,7 +10,8 @@
 // are found again (closure, driven from mesh.cpp).  Nodes are points of the
 // finest grid (level kMaxLevels), keyed by 21-bit coordinates.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "kuhn_dev.h"
 #include "mesh_internal.h"
@@ -418,7 +419,8 @@ hipError_t launch_tet_counts(const LevelPtrs &L, int l, const int32_t *list, int
 
 hipError_t exclusive_sum_i32(const int32_t *in, int64_t *out, int64_t n, void *tmp,
                              size_t *tmp_bytes, hipStream_t s) {
-    return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, s);
+    return rocprim::exclusive_scan(tmp, *tmp_bytes, in, out, (int64_t)0, (size_t)n,
+                                   rocprim::plus<int64_t>(), s);
 }
 
 hipError_t launch_emit(const LevelPtrs &L, const LatticeGeom &g, int l, const int32_t *list,
@@ -431,15 +433,18 @@ hipError_t launch_emit(const LevelPtrs &L, const LatticeGeom &g, int l, const in
 
 hipError_t sort_keys_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
                          hipStream_t s) {
-    return hipcub::DeviceRadixSort::SortKeys(tmp, *tmp_bytes, in, out, (int)n, 0, 64, s);
+    return rocprim::radix_sort_keys(tmp, *tmp_bytes, in, out, (size_t)n, 0u, 64u, s);
 }
 
 hipError_t launch_unique(const int64_t *sorted, int64_t n, int32_t *head, int64_t *pos,
                          int64_t *nodes, void *tmp, size_t *tmp_bytes, hipStream_t s) {
-    if (!tmp) return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, head, pos, (int)n, s);
+    if (!tmp)
+        return rocprim::exclusive_scan(tmp, *tmp_bytes, head, pos, (int64_t)0, (size_t)n,
+                                       rocprim::plus<int64_t>(), s);
     if (n <= 0) return hipSuccess;
     k_head_flags<<<grid_of(n), 256, 0, s>>>(sorted, n, head);
-    hipError_t e = hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, head, pos, (int)n, s);
+    hipError_t e = rocprim::exclusive_scan(tmp, *tmp_bytes, head, pos, (int64_t)0, (size_t)n,
+                                           rocprim::plus<int64_t>(), s);
     if (e != hipSuccess) return e;
     k_unique_scatter<<<grid_of(n), 256, 0, s>>>(sorted, head, pos, n, nodes);
     return hipGetLastError();

@@ -8,7 +8,7 @@
 // and sums rounded one by one, on the triangle's vertices in lexicographic
 // order, so the parameter depends on the geometry alone.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "post_internal.h"
 
@@ -275,7 +275,8 @@ hipError_t launch_bin_triangles(const float *tri, int64_t n_tri, const LatticeGe
 
 hipError_t exclusive_sum_bins(const int32_t *count, int64_t *start, int64_t n, void *tmp, size_t *tmp_bytes,
                               hipStream_t s) {
-    return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, count, start, (int)n, s);
+    return rocprim::exclusive_scan(tmp, *tmp_bytes, count, start, (int64_t)0, (size_t)n,
+                                   rocprim::plus<int64_t>(), s);
 }
 
 hipError_t launch_inflate(const float4 *in, float4 *out, const uint64_t *seg, const uint32_t *cols,

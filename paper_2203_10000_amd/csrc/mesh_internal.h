@@ -143,7 +143,7 @@ hipError_t launch_pattern_fresh(const LevelPtrs &L, const LatticeGeom &g, int l,
 // hist: 4 counters (leaves cut into 1, 2, 3, 4 tetrahedra), accumulated.
 hipError_t launch_tet_counts(const LevelPtrs &L, int l, const int32_t *list, int64_t count,
                              int32_t *counts, unsigned long long *hist, hipStream_t s);
-// hipCUB device-wide primitives: with tmp == nullptr they only set *tmp_bytes.
+// rocPRIM device-wide primitives: with tmp == nullptr they only set *tmp_bytes.
 hipError_t exclusive_sum_i32(const int32_t *in, int64_t *out, int64_t n, void *tmp,
                              size_t *tmp_bytes, hipStream_t s);
 hipError_t sort_keys_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,

@@ -7,7 +7,8 @@
 // bound by memory traffic; the arithmetic is a few double operations per
 // neighbour.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "post_internal.h"
 
@@ -316,7 +317,7 @@ hipError_t launch_edge_occurrences(const int32_t *ids, const int32_t *labels, in
 
 hipError_t sort_keys_u64(const uint64_t *in, uint64_t *out, int64_t n, int end_bit, void *tmp,
                          size_t *tmp_bytes, hipStream_t s) {
-    return hipcub::DeviceRadixSort::SortKeys(tmp, *tmp_bytes, in, out, (int)n, 0, end_bit, s);
+    return rocprim::radix_sort_keys(tmp, *tmp_bytes, in, out, (size_t)n, 0u, (unsigned)end_bit, s);
 }
 
 hipError_t launch_edge_heads(const uint64_t *keys, int64_t n, int32_t *head, hipStream_t s) {
@@ -327,7 +328,8 @@ hipError_t launch_edge_heads(const uint64_t *keys, int64_t n, int32_t *head, hip
 
 hipError_t exclusive_sum_head(const int32_t *head, int64_t *pos, int64_t n, void *tmp,
                               size_t *tmp_bytes, hipStream_t s) {
-    return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, head, pos, (int)n, s);
+    return rocprim::exclusive_scan(tmp, *tmp_bytes, head, pos, (int64_t)0, (size_t)n,
+                                   rocprim::plus<int64_t>(), s);
 }
 
 hipError_t launch_edge_directed(const uint64_t *keys, const int32_t *head, const int64_t *pos,
@@ -351,12 +353,12 @@ hipError_t launch_morton_order(const int64_t *keys, int64_t n, uint64_t *code, u
                                int32_t *ids, int32_t *order, int32_t *rank, void *tmp,
                                size_t *tmp_bytes, hipStream_t s) {
     if (!tmp)
-        return hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, code, code_sorted, ids, order, (int)n,
-                                                  0, 63, s);
+        return rocprim::radix_sort_pairs(tmp, *tmp_bytes, code, code_sorted, ids, order, (size_t)n,
+                                         0u, 63u, s);
     if (n <= 0) return hipSuccess;
     k_morton_codes<<<grid_of(n), kSmoothThreads, 0, s>>>(keys, n, code, ids);
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, code, code_sorted, ids, order,
-                                                      (int)n, 0, 63, s);
+    hipError_t e = rocprim::radix_sort_pairs(tmp, *tmp_bytes, code, code_sorted, ids, order,
+                                             (size_t)n, 0u, 63u, s);
     if (e != hipSuccess) return e;
     k_rank_of<<<grid_of(n), kSmoothThreads, 0, s>>>(order, n, rank);
     return hipGetLastError();
