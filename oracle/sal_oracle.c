@@ -284,9 +284,9 @@ static int resolve_threads(int n_threads)
     return c > 0 ? (int)c : 1;
 }
 
-/* Splits [0, n) into one contiguous range per thread (the last ranges take
- * the remainder); each index is computed by exactly one thread, so results do
- * not depend on the thread count. */
+/* Splits [0, n) into one contiguous range per thread, [n i / nt, n (i+1) / nt)
+ * (lengths differ by at most one); each index is computed by exactly one
+ * thread, so results do not depend on the thread count. */
 void oracle_parallel_for(int64_t n, int n_threads, range_fn fn, void *ctx)
 {
     int nt = resolve_threads(n_threads);
