@@ -115,6 +115,14 @@ typedef struct sal_surface_set_info {
 } sal_surface_set_info;
 sal_status sal_surface_set_get_info(const sal_surface_set *set, sal_surface_set_info *info);
 
+/* The validation and strip building of sal_surface_set_create (section
+ * 2.1.3: closed, consistently oriented segmentation boundaries) on the host
+ * alone, with no context and no device: the same checks and error statuses,
+ * and with SAL_OK `info` (if not NULL) gets what the set would hold
+ * (device_bytes: the bytes its creation would allocate).  Nothing is kept. */
+sal_status sal_surface_set_check(const sal_surface_desc *surfaces, int32_t n_surfaces,
+                                 uint32_t flags, sal_surface_set_info *info);
+
 /* ----------------------------------------------------------------- labeling
  * Precision forms of the pair loop:
  *   SAL_PREC_FP64          every (point, triangle) solid angle in double, with

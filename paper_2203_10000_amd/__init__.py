@@ -140,6 +140,8 @@ _SIGNATURES = [
      [_P, ctypes.POINTER(SurfaceDesc), ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(_P)]),
     ("sal_surface_set_destroy", None, [_P]),
     ("sal_surface_set_get_info", ctypes.c_int, [_P, ctypes.POINTER(SurfaceSetInfo)]),
+    ("sal_surface_set_check", ctypes.c_int,
+     [ctypes.POINTER(SurfaceDesc), ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(SurfaceSetInfo)]),
     ("sal_label_options_default", None, [ctypes.POINTER(LabelOptions)]),
     ("sal_label_points", ctypes.c_int,
      [_P, _P, ctypes.c_int64, _P, _P, _P, ctypes.POINTER(LabelOptions), _P, _P,
@@ -295,6 +297,27 @@ class SurfaceSet:
             self.close()
         except Exception:
             pass
+
+
+def surface_set_check(surfaces, auto_orient=False):
+    """sal_surface_set_check: validates surfaces (same list as SurfaceSet) on
+    the host, without a device; returns the info dict or raises SalError."""
+    keep = []
+    descs = (SurfaceDesc * len(surfaces))()
+    for i, s in enumerate(surfaces):
+        v, f, label = (s.v, s.f, s.label) if hasattr(s, "v") else s
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        f = np.ascontiguousarray(f, dtype=np.int32)
+        keep += [v, f]
+        descs[i].n_vertices = v.shape[0]
+        descs[i].xyz = v.ctypes.data
+        descs[i].n_triangles = f.shape[0]
+        descs[i].tri = f.ctypes.data
+        descs[i].label = int(label)
+    info = SurfaceSetInfo()
+    _check(lib().sal_surface_set_check(descs, len(surfaces), SURF_AUTO_ORIENT if auto_orient else 0,
+                                       ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in info._fields_}
 
 
 def surface_set_create(ctx, surfaces, auto_orient=False):

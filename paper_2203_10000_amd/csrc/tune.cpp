@@ -13,14 +13,15 @@
 #include <tuple>
 
 #include "runtime.h"
+#include "tune_cache.h"
 
 namespace sal {
 namespace {
 
-using Key = std::tuple<int, int, int, int, std::string, int, int>;
+using Key = TuneKey;
 
 std::mutex g_mu;
-std::map<Key, std::pair<int, int>> g_cache;
+TuneMap g_cache;
 bool g_loaded = false;
 
 constexpr int64_t kTrialPoints = (int64_t)1 << 19;   // enough workgroups to fill the device
@@ -43,28 +44,12 @@ std::string arch_name(int device) {
 void load_file() {
     g_loaded = true;
     const char *path = std::getenv("SAL_TUNE_CACHE");
-    if (!path) return;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return;
-    char arch[128];
-    int dev, prec, tb, nb, rp, rb, ppl, bw;
-    while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %d", arch, &dev, &prec, &tb, &nb, &rp, &rb,
-                       &ppl, &bw) == 9)
-        g_cache[Key(dev, prec, tb, nb, arch, rp, rb)] = {ppl, bw};
-    std::fclose(f);
+    if (path) tune_cache_read(path, &g_cache);
 }
 
 void save_file() {
     const char *path = std::getenv("SAL_TUNE_CACHE");
-    if (!path) return;
-    FILE *f = std::fopen(path, "w");
-    if (!f) return;
-    for (const auto &kv : g_cache)
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", std::get<4>(kv.first).c_str(),
-                     std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                     std::get<3>(kv.first), std::get<5>(kv.first), std::get<6>(kv.first),
-                     kv.second.first, kv.second.second);
-    std::fclose(f);
+    if (path) tune_cache_write(path, g_cache);
 }
 
 }  // namespace
