@@ -221,6 +221,29 @@ sal_status sal_label_points(sal_context *ctx, const sal_surface_set *set, int64_
                             const sal_label_options *opt, int32_t *labels, void *winding,
                             sal_label_stats *stats);
 
+/* sal_label_points for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (labels; winding numbers
+ * to the float32 form's tolerance, bit for bit with the same launch shape)
+ * as sal_label_points, but the call allocates nothing: its scratch (counters,
+ * flag list, recheck buffers, about 38 MB) is one static device array per
+ * GPU, held until the process ends, and its counters are cleared by a fill
+ * kernel on every call.  Limits and differences:
+ *   n_points  at most 1048576 per call (SAL_ERR_CAPACITY beyond; label larger
+ *             sets in chunks);
+ *   opt       cull_bounds must be 0 (SAL_ERR_INVALID_ARG); a launch shape left
+ *             at 0 is not tuned but set to 1 point per lane and 4 wavefronts
+ *             per workgroup (no trial launches, no synchronisation);
+ *   stats     NULL for a call that must not synchronise (filled, as in
+ *             sal_label_points, after synchronising the stream).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap in time on one GPU (other streams, other
+ * contexts, other threads) race and must be serialised by the caller. */
+sal_status sal_label_points_noalloc(sal_context *ctx, const sal_surface_set *set,
+                                    int64_t n_points, const float *x, const float *y,
+                                    const float *z, const sal_label_options *opt,
+                                    int32_t *labels, void *winding, sal_label_stats *stats);
+
 /* ----------------------------------------------------------- tetrahedral mesh
  * A Kuhn lattice (section 2.1.1) with nested red refinement (section 2.1.2).
  *

@@ -146,6 +146,9 @@ _SIGNATURES = [
     ("sal_label_points", ctypes.c_int,
      [_P, _P, ctypes.c_int64, _P, _P, _P, ctypes.POINTER(LabelOptions), _P, _P,
       ctypes.POINTER(LabelStats)]),
+    ("sal_label_points_noalloc", ctypes.c_int,
+     [_P, _P, ctypes.c_int64, _P, _P, _P, ctypes.POINTER(LabelOptions), _P, _P,
+      ctypes.POINTER(LabelStats)]),
     ("sal_tet_mesh_create_lattice", ctypes.c_int,
      [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
       ctypes.POINTER(_P)]),
@@ -344,6 +347,28 @@ def label_points(ctx, sset, points, precision="fp32", winding=None, stats=False,
     _check(lib().sal_label_points(ctx.handle, sset.handle, n, _ptr(x), _ptr(y), _ptr(z),
                                   ctypes.byref(o), _ptr(labels), _ptr(w),
                                   ctypes.byref(st) if st is not None else None))
+    return labels, w, (st.as_dict() if st is not None else None)
+
+
+def label_points_noalloc(ctx, sset, points, precision="fp32", winding=None, stats=False,
+                         out=None, **opt):
+    """sal_label_points_noalloc (same arguments and results as label_points;
+    at most 2^20 points; the library allocates no device memory)."""
+    import torch
+    x, y, z = (points[0], points[1], points[2])
+    for t in (x, y, z):
+        assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous()
+    n = x.numel()
+    labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=x.device)
+    w = None
+    if winding is not None:
+        dt = torch.float32 if winding == "f32" else torch.float64
+        w = torch.empty((sset.n_surfaces, n), dtype=dt, device=x.device)
+    o = label_options(precision=precision, winding=winding, **opt)
+    st = LabelStats() if stats else None
+    _check(lib().sal_label_points_noalloc(ctx.handle, sset.handle, n, _ptr(x), _ptr(y), _ptr(z),
+                                          ctypes.byref(o), _ptr(labels), _ptr(w),
+                                          ctypes.byref(st) if st is not None else None))
     return labels, w, (st.as_dict() if st is not None else None)
 
 

@@ -74,10 +74,24 @@ sal_status resolve_options(const sal_label_options *in, sal_label_options *out) 
     return SAL_OK;
 }
 
+LabelScratch context_scratch(const sal_context *ctx) {
+    return LabelScratch{ctx->counters, ctx->flag_list, ctx->rc_pairs, ctx->rc_out,
+                        ctx->rc_res,   ctx->rc_seg,    ctx->rc_pair_cap};
+}
+
 sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_t n,
                             const int64_t *n_dev, const float *x, const float *y, const float *z,
                             const sal_label_options &opt, int32_t *labels, void *winding,
                             hipEvent_t ev_mid, hipStream_t stream, unsigned long long *masks) {
+    return enqueue_label_with(ctx, set, n, n_dev, x, y, z, opt, labels, winding, ev_mid, stream,
+                              masks, context_scratch(ctx));
+}
+
+sal_status enqueue_label_with(sal_context *ctx, const sal_surface_set *set, int64_t n,
+                              const int64_t *n_dev, const float *x, const float *y,
+                              const float *z, const sal_label_options &opt, int32_t *labels,
+                              void *winding, hipEvent_t ev_mid, hipStream_t stream,
+                              unsigned long long *masks, const LabelScratch &sc) {
     PairloopArgs a{};
     a.rec32 = set->rec32;
     a.rec64 = set->rec64;
@@ -97,8 +111,8 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     if (!winding) a.winding = nullptr;
     a.masks = masks;
     a.cull = opt.cull_bounds ? 1 : 0;
-    a.flag_list = ctx->flag_list;
-    a.counters = ctx->counters;
+    a.flag_list = sc.flag_list;
+    a.counters = sc.counters;
     if (opt.precision == SAL_PREC_FP64) {
         SAL_HIP(launch_pairloop_f64(a, opt.block_waves, stream));
         if (ev_mid) SAL_HIP(hipEventRecord(ev_mid, stream));
@@ -121,14 +135,14 @@ sal_status enqueue_label_on(sal_context *ctx, const sal_surface_set *set, int64_
     r.winding = a.winding;
     r.winding_type = a.winding_type;
     r.masks = masks;
-    r.flag_list = ctx->flag_list;
-    r.counters = ctx->counters;
+    r.flag_list = sc.flag_list;
+    r.counters = sc.counters;
     r.n_surf = set->n_surf;
-    r.pairs = ctx->rc_pairs;
-    r.pair_out = ctx->rc_out;
-    r.res = ctx->rc_res;
-    r.seg = ctx->rc_seg;
-    r.pair_cap = ctx->rc_pair_cap;
+    r.pairs = sc.rc_pairs;
+    r.pair_out = sc.rc_out;
+    r.res = sc.rc_res;
+    r.seg = sc.rc_seg;
+    r.pair_cap = sc.rc_pair_cap;
     r.target_waves = (int64_t)ctx->n_cu * 32;
     const int64_t grid = n < (int64_t)ctx->n_cu * 8 ? n : (int64_t)ctx->n_cu * 8;
     SAL_HIP(launch_recheck_f64(r, (int)grid, stream));
@@ -218,6 +232,9 @@ sal_status sal_context_create(int device, void *stream, sal_context **out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
     if (ctx->n_cu <= 0) ctx->n_cu = 256;
+    // set-up of sal_label_points_noalloc: its scratch array's address on
+    // this device (looked up once per device; a failure shows there)
+    (void)noalloc_scratch(device);
     for (auto &ev : ctx->ev) {
         e = hipEventCreate(&ev);
         if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipEventCreate"); }

@@ -82,6 +82,33 @@ sal_status enqueue_label(sal_context *ctx, const sal_surface_set *set, int64_t n
                          hipEvent_t ev_after_pairloop, int *shape = nullptr,
                          unsigned long long *masks = nullptr);
 
+// The device scratch one labeling pass works in: the counters, the flag list
+// (one entry per point at most) and the pair-major recheck buffers.
+struct LabelScratch {
+    unsigned long long *counters;
+    FlagEntry *flag_list;
+    RecheckPair *rc_pairs;
+    RecheckOut *rc_out;
+    unsigned long long *rc_res;
+    RecheckSeg *rc_seg;
+    int64_t rc_pair_cap;
+};
+
+// The context's own scratch (sized by ensure_flag_capacity).
+LabelScratch context_scratch(const sal_context *ctx);
+
+// The launches of one labeling pass with a resolved launch shape and the
+// given scratch, on `stream`; the counters must be cleared by the caller.
+sal_status enqueue_label_with(sal_context *ctx, const sal_surface_set *set, int64_t n,
+                              const int64_t *n_dev, const float *x, const float *y,
+                              const float *z, const sal_label_options &opt, int32_t *labels,
+                              void *winding, hipEvent_t ev_mid, hipStream_t stream,
+                              unsigned long long *masks, const LabelScratch &sc);
+
+// Address of the allocation-free entry point's scratch array on `device`
+// (looked up once per device, with the device current); nullptr on error.
+void *noalloc_scratch(int device);
+
 // The launches of one labeling pass with a resolved launch shape, on
 // `stream`.  With n_dev set the point count is read on the device and n is the
 // capacity the grids are sized for (the form a captured graph uses).
