@@ -395,7 +395,7 @@ typedef struct sal_smooth_params {
     int32_t max_iter_volume;
 } sal_smooth_params;
 
-void sal_smooth_params_default(sal_smooth_params *p); /* section 3's values */
+void sal_smooth_params_default(sal_smooth_params *p); /* the values of section 2.6.1 */
 
 typedef struct sal_smooth_info {
     int64_t n_edges;          /* edges of the conforming mesh */
@@ -456,7 +456,7 @@ typedef struct sal_inflate_info {
  * edges cross no triangle stay; all moves read the positions from before the
  * call.  Positions are kept in float32.  The surface set is the one the mesh
  * was labeled with, or any other on the same device.
- *   zeta  in [0, 1) (section 3 uses 0.05);  info  NULL, or filled
+ *   zeta  in [0, 1) (section 2.6.1 uses 0.05);  info  NULL, or filled
  * Errors: SAL_ERR_INVALID_ARG before sal_tet_mesh_conform or for zeta
  * outside [0, 1); SAL_ERR_CAPACITY as for sal_tet_mesh_smooth. */
 sal_status sal_tet_mesh_inflate(sal_context *ctx, sal_tet_mesh *mesh, const sal_surface_set *set,

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Paper section 2.2.2, zeta = 0.05 in section 3: the nodes of a compartment
+Paper section 2.2.2, zeta = 0.05 in section 2.6.1: the nodes of a compartment
 boundary dV are slid along their edges toward the points where those edges
 cross the segmentation surface S, x_i <- x_i + zeta d e, with e the unit
 vector along the edge and d the distance from x_i to S.  Read as:

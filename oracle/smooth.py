@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Paper section 2.2.1 (smoothing), parameters in section 3 (lambda = mu = 0.4,
+Paper section 2.2.1 (smoothing), parameters in section 2.6.1 (lambda = mu = 0.4,
 xi = 0.9 for the volume and 0.1 for the tissue boundaries).  The printed
 update sums neighbour positions, which cannot be meant (it is not invariant
 under translation); read as Taubin's method with the umbrella operator over
