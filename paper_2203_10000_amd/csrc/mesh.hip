@@ -150,18 +150,55 @@ __device__ __forceinline__ bool pred(const CompactSrc &s, int64_t i) {
     return s.flag ? (s.flag[i] & (s.mask ? s.mask : 0xffu)) != 0 : s.child[i] < 0;
 }
 
+// Each thread owns kScanItems consecutive entries of its tile: one 16-byte
+// load of flag bytes (or four of int32 children) instead of one narrow load
+// per entry.  Returns the entries' predicate bits (bit j: entry first + j).
+// The wide loads need the whole run inside [0, n) and a 16-byte aligned
+// base; otherwise (the tail, or a misaligned array) entries are read one by one.
+static_assert(kScanItems == 16, "one 16-byte flag load per thread");
+__device__ __forceinline__ uint32_t pred_bits(const CompactSrc &s, int64_t first, int64_t n) {
+    uint32_t bits = 0;
+    const bool whole = first + kScanItems <= n;
+    if (s.flag) {
+        const uint32_t mk = s.mask ? s.mask : 0xffu;
+        if (whole && (((uintptr_t)(s.flag + first)) & 15u) == 0) {
+            const uint4 w = *(const uint4 *)(s.flag + first);
+            const uint32_t m4 = mk * 0x01010101u;
+            const uint32_t words[4] = {w.x & m4, w.y & m4, w.z & m4, w.w & m4};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    bits |= (((words[q] >> (8 * b)) & 0xffu) != 0u ? 1u : 0u) << (4 * q + b);
+        } else {
+            for (int j = 0; j < kScanItems; ++j)
+                if (first + j < n && (s.flag[first + j] & mk) != 0) bits |= 1u << j;
+        }
+    } else {
+        if (whole && (((uintptr_t)(s.child + first)) & 15u) == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int4 c = *(const int4 *)(s.child + first + 4 * q);
+                bits |= (c.x < 0 ? 1u : 0u) << (4 * q);
+                bits |= (c.y < 0 ? 1u : 0u) << (4 * q + 1);
+                bits |= (c.z < 0 ? 1u : 0u) << (4 * q + 2);
+                bits |= (c.w < 0 ? 1u : 0u) << (4 * q + 3);
+            }
+        } else {
+            for (int j = 0; j < kScanItems; ++j)
+                if (first + j < n && s.child[first + j] < 0) bits |= 1u << j;
+        }
+    }
+    return bits;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_count(CompactSrc s, int64_t n,
                                                         const int64_t *__restrict__ n_dev,
                                                         int64_t *__restrict__ block_counts) {
     __shared__ int red[kScanThreads];
     if (n_dev) n = *n_dev;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    int cnt = 0;
-    for (int r = 0; r < kScanItems; ++r) {
-        const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-        if (i < n && pred(s, i)) ++cnt;
-    }
-    red[threadIdx.x] = cnt;
+    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    red[threadIdx.x] = first < n ? __popc(pred_bits(s, first, n)) : 0;
     __syncthreads();
     for (int w = kScanThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -196,12 +233,12 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int64_t *__restrict__ coun
     if (t == 1023) *total = part[1023];
 }
 
-// Ordered scatter of one tile: each wavefront takes a contiguous quarter of
-// the tile in 64-entry steps (coalesced reads), ranks its matches with
-// ballots, and the tile's indices are staged in LDS in index order, then
-// written out contiguously (coalesced writes).
+// Ordered scatter of one tile: thread t owns the kScanItems consecutive
+// entries starting at tile + t kScanItems (so thread order is index order);
+// a scan of the per-thread counts across the workgroup gives each thread its
+// place, the tile's indices are staged in LDS in index order, then written
+// out contiguously (coalesced writes).
 constexpr int kScanWaves = kScanThreads / 64;
-constexpr int kWaveItems = kScanTile / kScanWaves;
 
 __global__ __launch_bounds__(kScanThreads) void k_scatter(CompactSrc s, int64_t n,
                                                           const int64_t *__restrict__ n_dev,
@@ -212,26 +249,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter(CompactSrc s, int64_t 
     if (n_dev) n = *n_dev;
     const int lane = (int)(threadIdx.x & 63u);
     const int wv = (int)(threadIdx.x >> 6);
-    const int64_t wbase = (int64_t)blockIdx.x * kScanTile + (int64_t)wv * kWaveItems;
-    const uint64_t below = (1ull << lane) - 1ull;
-    int cnt = 0;
-    for (int r = 0; r < kWaveItems / 64; ++r) {
-        const int64_t i = wbase + r * 64 + lane;
-        cnt += __popcll(__builtin_amdgcn_ballot_w64(i < n && pred(s, i)));
+    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t bits = first < n ? pred_bits(s, first, n) : 0u;
+    const int cnt = __popc(bits);
+    // inclusive scan of the counts over the wavefront's lanes
+    int inc = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
     }
-    if (lane == 0) wave_total[wv] = cnt;
+    if (lane == 63) wave_total[wv] = inc;
     __syncthreads();
     int run = 0, total = 0;
     for (int w = 0; w < kScanWaves; ++w) {
         if (w < wv) run += wave_total[w];
         total += wave_total[w];
     }
-    for (int r = 0; r < kWaveItems / 64; ++r) {
-        const int64_t i = wbase + r * 64 + lane;
-        const bool p = i < n && pred(s, i);
-        const uint64_t m = __builtin_amdgcn_ballot_w64(p);
-        if (p) buf[run + __popcll(m & below)] = (int32_t)i;
-        run += __popcll(m);
+    int pos = run + inc - cnt;
+    while (bits) {
+        const int j = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        buf[pos++] = (int32_t)(first + j);
     }
     __syncthreads();
     const int64_t o = offsets[blockIdx.x];

@@ -171,6 +171,18 @@ __device__ __forceinline__ void block_sum(double v, double *partials) {
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
+// As block_sum, into partials[at] (the block's tile in a remapped grid).
+__device__ __forceinline__ void block_sum_at(double v, double *partials, int64_t at) {
+    __shared__ double red[kSmoothThreads];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kSmoothThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[at] = red[0];
+}
+
 __global__ __launch_bounds__(kSmoothThreads) void k_norm_sq(const float4 *__restrict__ p,
                                                            const int32_t *__restrict__ list,
                                                            int64_t n, double *__restrict__ partials) {
@@ -234,7 +246,13 @@ __global__ __launch_bounds__(kSmoothThreads) void k_taubin_half(
 #pragma clang fp contract(off)
     constexpr int G = kTaubinGroup, U = kTaubinUnroll;
     const int lane = (int)(threadIdx.x & (G - 1));
-    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    // Workgroups go to the 8 XCDs round-robin; tile = the block's place in a
+    // grid where each XCD takes one contiguous eighth of the nodes (Morton
+    // order), so the neighbour positions a node gathers sit in the L2 of the
+    // XCD that gathers them (the grid is a multiple of 8 blocks).
+    const int64_t per = (int64_t)gridDim.x / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t t = (tile * blockDim.x + threadIdx.x) / G;
     double sx = 0.0, sy = 0.0, sz = 0.0;
     int cnt = 0;
     int32_t i = 0;
@@ -299,13 +317,18 @@ __global__ __launch_bounds__(kSmoothThreads) void k_taubin_half(
         const double dx = (double)o.x - xi.x, dy = (double)o.y - xi.y, dz = (double)o.z - xi.z;
         d2 = dx * dx + dy * dy + dz * dz;
     }
-    block_sum(d2, partials);
+    block_sum_at(d2, partials, tile);
 }
 
 }  // namespace
 
 int64_t smooth_blocks(int64_t n) { return (n + kSmoothThreads - 1) / kSmoothThreads; }
-int64_t taubin_blocks(int64_t n) { return (n * kTaubinGroup + kSmoothThreads - 1) / kSmoothThreads; }
+// Blocks of a half step, rounded up to a multiple of the 8 XCDs (the
+// trailing blocks find no node and add 0 to the stopping sum).
+int64_t taubin_blocks(int64_t n) {
+    const int64_t b = (n * kTaubinGroup + kSmoothThreads - 1) / kSmoothThreads;
+    return (b + 7) / 8 * 8;
+}
 
 hipError_t launch_edge_occurrences(const int32_t *ids, const int32_t *labels, int64_t n_tets,
                                    uint64_t *keys, unsigned long long *bad_labels, hipStream_t s) {

@@ -1,6 +1,7 @@
-"""Parity at the full workload sizes (the benchmark's launch configurations),
-on outputs the FP64 oracle can compute one by one: a uniform sample plus a
-sample near the surfaces, where labels are hardest."""
+"""Parity at the full workload sizes (the benchmark's launch configurations):
+every label against the oracle's exact radial point-in-polyhedron test (all
+synthetic surfaces are star-shaped about known centres), and a uniform plus a
+near-surface sample against the FP64 winding-number oracle itself."""
 import numpy as np
 import pytest
 
@@ -28,9 +29,26 @@ def _sample(rng, n_all, n, near_mask=None):
     return np.unique(idx)
 
 
+def test_c2_full_size_every_label_and_fp64_form(ctx):
+    """Four shells (81,920 triangles), 6M lattice centroids: every FP32+recheck
+    label equals the radial test's and the plain FP64 form's."""
+    cfg = synth.config_c2()
+    lat = cfg.lattice
+    ss = sal.SurfaceSet(ctx, cfg.surfaces)
+    mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
+    cen = mesh.export(keys=False, labels=False, centroids=True)["centroids"]
+    l32, _, _ = sal.label_points(ctx, ss, cen, precision="fp32")
+    l64, _, _ = sal.label_points(ctx, ss, cen, precision="fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(l32, l64)
+    m, bad = oracle.RadialSet(cfg.surfaces).check_lattice(lat, l32.cpu().numpy(),
+                                                          n_threads=oracle.host_threads())
+    assert m == 0, bad
+
+
 def test_c3_full_size_two_rounds(ctx):
     """20 compartments (409,600 triangles), 48M-centroid lattice, two
-    refine-and-relabel rounds (1.06e8 leaves)."""
+    refine-and-relabel rounds (1.06e8 leaves): every leaf label exact."""
     cfg = synth.config_c3()
     lat = cfg.lattice
     ss = sal.SurfaceSet(ctx, cfg.surfaces)
@@ -40,12 +58,16 @@ def test_c3_full_size_two_rounds(ctx):
     assert level == 2
     assert n_leaves == lat.n_points + 7 * sum(r["n_boundary"] for r in st)
     assert all(r["n_boundary"] > 0 for r in st[1:])
-    e = mesh.export(keys=False, labels=True, centroids=True)
+    e = mesh.export(keys=True, labels=True, centroids=True)
     torch.cuda.synchronize()
     lab = e["labels"].cpu().numpy()
     cen = e["centroids"].cpu().numpy()
+    keys = e["keys"].cpu().numpy().view(np.uint64)
     del e
     assert np.all(lab >= 0)
+    m, bad = oracle.RadialSet(cfg.surfaces).check_keys(lat.origin, lat.h, keys, lab,
+                                                       n_threads=oracle.host_threads())
+    assert m == 0, bad
     rng = np.random.default_rng(301)
     r = np.linalg.norm(cen.astype(np.float64), axis=0)
     near = np.min(np.abs(r[:, None] - np.array([92, 86, 80, 76.0])), axis=1) < 3.0
@@ -81,6 +103,10 @@ def test_c4_full_size_batched(ctx):
         idx = _sample(rng, pts.shape[1], 300)
         want = oracle.label(np.ascontiguousarray(pts[:, idx]), surfs)
         assert np.array_equal(a.cpu().numpy()[idx], want)
+    # every label of every instance by the radial test
+    for (surfs, pts), a in zip(insts, per):
+        want = oracle.RadialSet(surfs).label(pts, n_threads=oracle.host_threads())
+        assert np.array_equal(a.cpu().numpy(), want)
 
 
 def test_c5_surfaces_near_surface_points(ctx):
@@ -99,6 +125,8 @@ def test_c5_surfaces_near_surface_points(ctx):
     idx = _sample(rng, len(lab), 1200)
     want = oracle.label(np.ascontiguousarray(cfg.points[:, idx]), cfg.surfaces)
     assert np.array_equal(lab[idx], want)
+    radial = oracle.RadialSet(cfg.surfaces)
+    assert np.array_equal(lab, radial.label(cfg.points, n_threads=oracle.host_threads()))
 
 
 def _tet_volumes6(pts, tets, chunk=1 << 24):
@@ -141,6 +169,12 @@ def test_c3_full_size_post_processing(ctx):
     ss = sal.SurfaceSet(ctx, cfg.surfaces)
     mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
     mesh.refine_relabel(ss, cfg.rounds, rule="four_nodes")
+    k = mesh.export(keys=True, labels=True, centroids=False)
+    m, bad = oracle.RadialSet(cfg.surfaces).check_keys(
+        lat.origin, lat.h, k["keys"].cpu().numpy().view(np.uint64), k["labels"].cpu().numpy(),
+        rule="four_nodes", n_threads=oracle.host_threads())
+    assert m == 0, bad                          # every leaf under the four-node rule
+    del k
     info = mesh.conform()
     e = mesh.export_conforming()
     keys = e["node_keys"]
