@@ -68,6 +68,13 @@ const char *sal_last_error_message(void);
 /* SAL_ABI_VERSION of the loaded library. */
 int sal_abi_version(void);
 
+/* Fault injection for tests of the error paths: with n > 0 the n-th device
+ * allocation the library makes from now on (in any thread) fails once, as if
+ * the device were out of memory (the call that makes it returns
+ * SAL_ERR_OUT_OF_MEMORY, or SAL_ERR_DEVICE where a HIP error is reported as
+ * such); n <= 0 disarms it.  Nothing else changes: no kernel sees it. */
+void sal_debug_fail_allocation(int64_t n);
+
 typedef struct sal_context sal_context;
 typedef struct sal_surface_set sal_surface_set;
 typedef struct sal_tet_mesh sal_tet_mesh;

@@ -140,6 +140,7 @@ _SIGNATURES = [
      [_P, ctypes.POINTER(SurfaceDesc), ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(_P)]),
     ("sal_surface_set_destroy", None, [_P]),
     ("sal_surface_set_get_info", ctypes.c_int, [_P, ctypes.POINTER(SurfaceSetInfo)]),
+    ("sal_debug_fail_allocation", None, [ctypes.c_int64]),
     ("sal_surface_set_check", ctypes.c_int,
      [ctypes.POINTER(SurfaceDesc), ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(SurfaceSetInfo)]),
     ("sal_label_options_default", None, [ctypes.POINTER(LabelOptions)]),

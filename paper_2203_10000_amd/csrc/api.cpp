@@ -1,4 +1,5 @@
 // C-ABI entry points: contexts, surface sets, point labeling.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -13,6 +14,21 @@ static thread_local std::string g_last_error;
 sal_status set_error(sal_status s, const std::string &msg) {
     g_last_error = msg;
     return s;
+}
+
+// Allocation fault injection (sal_debug_fail_allocation): the countdown is
+// the number of allocations left before the one that fails; 0 = off.
+static std::atomic<int64_t> g_fail_countdown{0};
+
+hipError_t dev_malloc(void **ptr, size_t bytes) {
+    int64_t c = g_fail_countdown.load();
+    while (c > 0 && !g_fail_countdown.compare_exchange_weak(c, c - 1)) {
+    }
+    if (c == 1) {
+        if (ptr) *ptr = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(ptr, bytes);
 }
 
 sal_status hip_error(hipError_t e, const char *what) {
@@ -39,11 +55,11 @@ sal_status ensure_flag_capacity(sal_context *ctx, int64_t n) {
     ctx->rc_pair_cap = 0;
     const int64_t cap = n < 4096 ? 4096 : n;
     const int64_t pcap = cap / 4 + 64 * kMaxSurfaces;
-    SAL_HIP(hipMalloc((void **)&ctx->flag_list, (size_t)cap * sizeof(FlagEntry)));
-    SAL_HIP(hipMalloc((void **)&ctx->rc_res, (size_t)cap * sizeof(unsigned long long)));
-    SAL_HIP(hipMalloc((void **)&ctx->rc_pairs, (size_t)pcap * sizeof(RecheckPair)));
-    SAL_HIP(hipMalloc((void **)&ctx->rc_out, (size_t)pcap * sizeof(RecheckOut)));
-    if (!ctx->rc_seg) SAL_HIP(hipMalloc((void **)&ctx->rc_seg, sizeof(RecheckSeg)));
+    SAL_HIP(dev_malloc((void **)&ctx->flag_list, (size_t)cap * sizeof(FlagEntry)));
+    SAL_HIP(dev_malloc((void **)&ctx->rc_res, (size_t)cap * sizeof(unsigned long long)));
+    SAL_HIP(dev_malloc((void **)&ctx->rc_pairs, (size_t)pcap * sizeof(RecheckPair)));
+    SAL_HIP(dev_malloc((void **)&ctx->rc_out, (size_t)pcap * sizeof(RecheckOut)));
+    if (!ctx->rc_seg) SAL_HIP(dev_malloc((void **)&ctx->rc_seg, sizeof(RecheckSeg)));
     ctx->flag_cap = cap;
     ctx->rc_pair_cap = pcap;
     return SAL_OK;
@@ -202,6 +218,8 @@ const char *sal_last_error_message(void) { return g_last_error.c_str(); }
 
 int sal_abi_version(void) { return SAL_ABI_VERSION; }
 
+void sal_debug_fail_allocation(int64_t n) { g_fail_countdown.store(n > 0 ? n : 0); }
+
 void sal_label_options_default(sal_label_options *o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
@@ -239,11 +257,11 @@ sal_status sal_context_create(int device, void *stream, sal_context **out) {
         e = hipEventCreate(&ev);
         if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipEventCreate"); }
     }
-    e = hipMalloc((void **)&ctx->counters, kNumCounters * sizeof(unsigned long long));
+    e = dev_malloc((void **)&ctx->counters, kNumCounters * sizeof(unsigned long long));
     if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(counters)"); }
-    e = hipMalloc((void **)&ctx->tune_counters, kNumCounters * sizeof(unsigned long long));
+    e = dev_malloc((void **)&ctx->tune_counters, kNumCounters * sizeof(unsigned long long));
     if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(counters)"); }
-    e = hipMalloc((void **)&ctx->batch_next, sizeof(unsigned int) * 4);
+    e = dev_malloc((void **)&ctx->batch_next, sizeof(unsigned int) * 4);
     if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipMalloc(batch counter)"); }
     e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) { sal_context_destroy(ctx); return hip_error(e, "hipStreamCreate"); }

@@ -19,7 +19,7 @@ sal_status ensure_dev(T **p, int64_t *have, int64_t need, hipStream_t s, sal_con
     *p = nullptr;
     *have = 0;
     const int64_t cap = need + need / 4 + 64;
-    SAL_HIP(hipMalloc((void **)p, (size_t)cap * sizeof(T)));
+    SAL_HIP(dev_malloc((void **)p, (size_t)cap * sizeof(T)));
     *have = cap;
     ctx->batch_graph_key = 0;   // buffers moved: a captured graph is stale
     return SAL_OK;
@@ -210,8 +210,8 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
                 ctx->batch_slots = 0;
                 ctx->batch_graph_key = 0;
                 const int64_t cap_slots = slot + slot / 4 + 64;
-                SAL_HIP(hipMalloc((void **)&ctx->batch_partial, (size_t)cap_slots * 64 * sizeof(double)));
-                SAL_HIP(hipMalloc((void **)&ctx->batch_mask, (size_t)cap_slots * sizeof(uint64_t)));
+                SAL_HIP(dev_malloc((void **)&ctx->batch_partial, (size_t)cap_slots * 64 * sizeof(double)));
+                SAL_HIP(dev_malloc((void **)&ctx->batch_mask, (size_t)cap_slots * sizeof(uint64_t)));
                 ctx->batch_slots = cap_slots;
             }
             // the previous call may still read these buffers

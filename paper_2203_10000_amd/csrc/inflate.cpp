@@ -19,7 +19,7 @@ struct Buffers {
     }
     template <typename T>
     sal_status get(T **out, int64_t n) {
-        if (hipMalloc((void **)out, (size_t)std::max<int64_t>(n, 1) * sizeof(T)) != hipSuccess)
+        if (dev_malloc((void **)out, (size_t)std::max<int64_t>(n, 1) * sizeof(T)) != hipSuccess)
             return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(inflation)");
         p.push_back(*out);
         return SAL_OK;

@@ -122,7 +122,7 @@ sal::LevelPtrs ptrs(const sal_tet_mesh *m) {
 template <typename T>
 sal_status grow(T **p, int64_t old_n, int64_t new_cap, hipStream_t s) {
     T *q = nullptr;
-    SAL_HIP(hipMalloc((void **)&q, (size_t)new_cap * sizeof(T)));
+    SAL_HIP(dev_malloc((void **)&q, (size_t)new_cap * sizeof(T)));
     if (*p && old_n > 0)
         SAL_HIP(hipMemcpyAsync(q, *p, (size_t)old_n * sizeof(T), hipMemcpyDeviceToDevice, s));
     if (*p) {
@@ -222,8 +222,12 @@ sal_status ensure_node_table(sal_tet_mesh *m, int64_t more, hipStream_t s) {
     int64_t cap = 1 << 16;
     while (cap < need) cap <<= 1;
     unsigned long long *k = nullptr, *v = nullptr;
-    SAL_HIP(hipMalloc((void **)&k, (size_t)cap * sizeof(unsigned long long)));
-    SAL_HIP(hipMalloc((void **)&v, (size_t)cap * sizeof(unsigned long long)));
+    SAL_HIP(dev_malloc((void **)&k, (size_t)cap * sizeof(unsigned long long)));
+    const hipError_t ev = dev_malloc((void **)&v, (size_t)cap * sizeof(unsigned long long));
+    if (ev != hipSuccess) {
+        (void)hipFree(k);
+        return hip_error(ev, "hipMalloc(node table)");
+    }
     SAL_HIP(launch_fill_u64(k, ~0ull, cap, s));
     if (m->tkeys) {
         SAL_HIP(launch_node_rehash(m->tkeys, m->tmasks, m->tcap, k, v, cap, s));
@@ -278,6 +282,44 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
         return set_error(SAL_ERR_CAPACITY, "refinement beyond level 3");
     int64_t n_split = 0, n_label = 0;
     float ms_split = 0.0f, ms_label = 0.0f, ms_recheck = 0.0f;
+    // Every buffer the round needs is allocated before the first split, so a
+    // round that runs out of device memory fails with the mesh unchanged
+    // (the in-loop ensure calls below then find the room already there).
+    {
+        const bool nodes = m->rule == SAL_RULE_FOUR_NODES;
+        int64_t pts_max = 0, pts_sum = 0;
+        for (int l = top; l >= 0; --l) {
+            if (count[l] == 0) continue;
+            const int64_t n_pts = nodes ? 6 * count[l] : 8 * count[l];
+            pts_max = std::max(pts_max, n_pts);
+            pts_sum += n_pts;
+            if ((st = ensure_level(m, l + 1, m->n[l + 1] + 8 * count[l], s)) != SAL_OK) return st;
+        }
+        if (pts_max > 0) {
+            if ((st = ensure_centroids(m, pts_max, s)) != SAL_OK) return st;
+            if (opt.precision == SAL_PREC_FP32_RECHECK &&
+                (st = ensure_flag_capacity(ctx, pts_max)) != SAL_OK)
+                return st;
+            if (nodes) {
+                int64_t c3 = m->mid_xyz_cap;
+                for (int a = 0; a < 3; ++a) {
+                    c3 = m->mid_xyz_cap;
+                    if ((st = ensure_buf(&m->mid_xyz[a], &c3, pts_max, s)) != SAL_OK) return st;
+                }
+                m->mid_xyz_cap = c3;
+                if ((st = ensure_buf(&m->lab_scratch, &m->lab_cap, pts_max, s)) != SAL_OK ||
+                    (st = ensure_buf(&m->mid_masks, &m->mid_cap, pts_max, s)) != SAL_OK ||
+                    (st = ensure_buf(&m->mid_key, &m->mid_key_cap, pts_max, s)) != SAL_OK ||
+                    (st = ensure_buf(&m->mid_slot, &m->mid_slot_cap, pts_max, s)) != SAL_OK ||
+                    (st = ensure_buf(&m->new_list, &m->new_list_cap, pts_max, s)) != SAL_OK ||
+                    (st = ensure_buf(&m->new_masks, &m->new_masks_cap, pts_max, s)) != SAL_OK ||
+                    (st = ensure_node_table(m, pts_sum, s)) != SAL_OK)
+                    return st;
+                if (!m->n_new && dev_malloc((void **)&m->n_new, sizeof(unsigned long long)) != hipSuccess)
+                    return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(node counter)");
+            }
+        }
+    }
     // deepest level first: its children array never moves under a pending
     // split of a coarser level
     for (int l = top; l >= 0; --l) {
@@ -302,7 +344,7 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
                 (st = ensure_buf(&m->new_masks, &m->new_masks_cap, n_pts, s)) != SAL_OK ||
                 (st = ensure_node_table(m, n_pts, s)) != SAL_OK)
                 return st;
-            if (!m->n_new && hipMalloc((void **)&m->n_new, sizeof(unsigned long long)) != hipSuccess)
+            if (!m->n_new && dev_malloc((void **)&m->n_new, sizeof(unsigned long long)) != hipSuccess)
                 return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(node counter)");
         }
         const int64_t base_block = m->n[l + 1] / 8;
@@ -324,6 +366,7 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
         }
         SAL_HIP(hipEventRecord(m->ev[6], s));
         m->n[l + 1] += kids;
+        m->n_leaves += 7 * count[l];
         if (nodes) {
             if ((st = label_scratch_dev(ctx, m, set, n_pts, m->n_new, opt, m->lab_scratch,
                                         m->ev[10], m->ev[9], m->new_masks)) != SAL_OK)
@@ -353,7 +396,6 @@ sal_status eager_round(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set 
             n_label += n_pts;
         }
     }
-    m->n_leaves += 7 * n_split;
     if (n_split_out) *n_split_out = n_split;
     SAL_HIP(hipEventRecord(m->ev[8], s));
     if (out) {
@@ -476,7 +518,7 @@ sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set
     }
     if ((st = ensure_buf(&m->list, &m->list_cap, list_need, s)) != SAL_OK) return st;
     if ((st = ensure_buf(&m->blocks, &m->blocks_cap, blocks_need, s)) != SAL_OK) return st;
-    if (!m->rs && hipMalloc((void **)&m->rs, sizeof(RoundState)) != hipSuccess)
+    if (!m->rs && dev_malloc((void **)&m->rs, sizeof(RoundState)) != hipSuccess)
         return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(round state)");
 
     // The launch shape is fixed in the graph: resolve it now (tuning
@@ -619,7 +661,7 @@ struct DevScratch {
     sal_status get(T **p, int64_t n) {
         void *q = nullptr;
         const size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
-        if (hipMalloc(&q, bytes) != hipSuccess) return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conform)");
+        if (dev_malloc(&q, bytes) != hipSuccess) return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conform)");
         bufs.push_back(q);
         *p = (T *)q;
         return SAL_OK;
@@ -641,7 +683,7 @@ struct GrowBuf {
         p = nullptr;
         cap = 0;
         const int64_t c = n + n / 4 + 1024;
-        if (hipMalloc((void **)&p, (size_t)c * sizeof(T)) != hipSuccess)
+        if (dev_malloc((void **)&p, (size_t)c * sizeof(T)) != hipSuccess)
             return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conform)");
         cap = c;
         return SAL_OK;
@@ -719,7 +761,7 @@ sal_status sal_tet_mesh_create_lattice(sal_context *ctx, const double origin[3],
             if (hipEventCreate(&e) != hipSuccess) return fail(set_error(SAL_ERR_DEVICE, "hipEventCreate"));
         if ((st = ensure_level(m, 0, n0, ctx->stream)) != SAL_OK) return fail(st);
         m->n[0] = n0;
-        if (hipMalloc((void **)&m->totals, (kMaxLevels + 1) * sizeof(int64_t)) != hipSuccess)
+        if (dev_malloc((void **)&m->totals, (kMaxLevels + 1) * sizeof(int64_t)) != hipSuccess)
             return fail(set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(totals)"));
         if (hipError_t e = launch_fill_i32(m->child[0], -1, n0, ctx->stream); e != hipSuccess)
             return fail(hip_error(e, "fill child"));
@@ -778,7 +820,7 @@ sal_status label_lattice(sal_context *ctx, sal_tet_mesh *m, const sal_surface_se
                                 (int64_t)(m->g.cells[2] + 1);
         if ((st = ensure_centroids(m, n_nodes, s)) != SAL_OK) return st;
         if ((st = ensure_buf(&m->lab_scratch, &m->lab_cap, n_nodes, s)) != SAL_OK) return st;
-        if (!m->node0 && hipMalloc((void **)&m->node0, (size_t)n_nodes * sizeof(uint64_t)) !=
+        if (!m->node0 && dev_malloc((void **)&m->node0, (size_t)n_nodes * sizeof(uint64_t)) !=
                              hipSuccess)
             return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(node masks)");
         SAL_HIP(launch_lattice_nodes(m->g, n_nodes, m->cen[0], m->cen[1], m->cen[2], s));
@@ -1071,9 +1113,9 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
             (st = keep.get(&pos, n_corner)) != SAL_OK || (st = keep.get(&head, n_corner)) != SAL_OK ||
             (st = keep.get(&nodes, n_corner)) != SAL_OK)
             return st;
-        if (hipMalloc((void **)&m->conf_labels, (size_t)std::max<int64_t>(n_tets, 1) * sizeof(int32_t)) !=
+        if (dev_malloc((void **)&m->conf_labels, (size_t)std::max<int64_t>(n_tets, 1) * sizeof(int32_t)) !=
                 hipSuccess ||
-            hipMalloc((void **)&m->conf_ids, (size_t)std::max<int64_t>(n_corner, 1) * sizeof(int32_t)) !=
+            dev_malloc((void **)&m->conf_ids, (size_t)std::max<int64_t>(n_corner, 1) * sizeof(int32_t)) !=
                 hipSuccess)
             return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conforming mesh)");
         LevelPtrs L = ptrs(m);
@@ -1095,9 +1137,9 @@ sal_status sal_tet_mesh_conform(sal_context *ctx, sal_tet_mesh *m, sal_conform_i
         SAL_HIP(hipMemcpyAsync(&last_head, head + n_corner - 1, sizeof(last_head), hipMemcpyDeviceToHost, s));
         SAL_HIP(hipStreamSynchronize(s));
         const int64_t n_nodes = last_pos + last_head;
-        if (hipMalloc((void **)&m->conf_keys, (size_t)std::max<int64_t>(n_nodes, 1) * sizeof(int64_t)) !=
+        if (dev_malloc((void **)&m->conf_keys, (size_t)std::max<int64_t>(n_nodes, 1) * sizeof(int64_t)) !=
                 hipSuccess ||
-            hipMalloc((void **)&m->conf_xyz, (size_t)std::max<int64_t>(3 * n_nodes, 1) * sizeof(float)) !=
+            dev_malloc((void **)&m->conf_xyz, (size_t)std::max<int64_t>(3 * n_nodes, 1) * sizeof(float)) !=
                 hipSuccess)
             return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(conforming nodes)");
         SAL_HIP(hipMemcpyAsync(m->conf_keys, nodes, (size_t)n_nodes * sizeof(int64_t), hipMemcpyDeviceToDevice, s));

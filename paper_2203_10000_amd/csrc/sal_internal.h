@@ -168,6 +168,10 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 
 // ------------------------------------------------------------ host helpers
 sal_status set_error(sal_status s, const std::string &msg);
+
+// Every device allocation of the library goes through here: hipMalloc, or a
+// simulated out-of-memory when sal_debug_fail_allocation armed this call.
+hipError_t dev_malloc(void **ptr, size_t bytes);
 sal_status hip_error(hipError_t e, const char *what);
 
 }  // namespace sal

@@ -33,7 +33,7 @@ int bits_for(int64_t n) {
 
 template <typename T>
 sal_status dev_alloc(T **p, int64_t n) {
-    if (hipMalloc((void **)p, (size_t)std::max<int64_t>(n, 1) * sizeof(T)) != hipSuccess)
+    if (dev_malloc((void **)p, (size_t)std::max<int64_t>(n, 1) * sizeof(T)) != hipSuccess)
         return set_error(SAL_ERR_OUT_OF_MEMORY, "hipMalloc(smoothing)");
     return SAL_OK;
 }

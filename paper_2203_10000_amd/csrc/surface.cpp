@@ -38,7 +38,7 @@ sal_status build_surface_set(sal_context *ctx, const sal_surface_desc *desc, int
     set->host_strip_tris = strip_tris;
     sal_status st = SAL_OK;
     auto up = [&](void **dst, const void *src, size_t bytes) -> sal_status {
-        hipError_t e = hipMalloc(dst, bytes);
+        hipError_t e = dev_malloc(dst, bytes);
         if (e != hipSuccess) return hip_error(e, "hipMalloc(surface set)");
         e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_error(e, "hipMemcpy(surface set)");
@@ -70,9 +70,9 @@ sal_status ensure_surface_balls(sal_context *ctx, const sal_surface_set *cset) {
     int32_t *dl = nullptr;
     unsigned long long *dm = nullptr;
     std::vector<unsigned long long> masks((size_t)n, 0);
-    hipError_t e = hipMalloc((void **)&dc, c.size() * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc((void **)&dl, (size_t)n * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc((void **)&dm, (size_t)n * sizeof(unsigned long long));
+    hipError_t e = dev_malloc((void **)&dc, c.size() * sizeof(float));
+    if (e == hipSuccess) e = dev_malloc((void **)&dl, (size_t)n * sizeof(int32_t));
+    if (e == hipSuccess) e = dev_malloc((void **)&dm, (size_t)n * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemcpy(dc, c.data(), c.size() * sizeof(float), hipMemcpyHostToDevice);
     // each centre against its own surface only: one FP64 launch per surface
     for (int i = 0; i < n && e == hipSuccess; ++i) {
