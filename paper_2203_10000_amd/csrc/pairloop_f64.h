@@ -41,7 +41,7 @@ struct Vtx {
 };
 
 struct Rec {
-    double v[8];         // Z, n, |B - A||C - A| (slightly enlarged), strip parity
+    double v[8];         // Z, n, 32 eps |B - A||C - A| (slightly enlarged), strip parity
 };
 
 // One 64-byte record from the constant address space: a single scalar load.
@@ -123,9 +123,6 @@ __device__ __noinline__ ExactN exact_step(float px, float py, float pz, const Re
 // hoisted out of the loop into some forty registers, which spilled.
 __device__ __noinline__ double atan2_ool(double y, double x) { return atan2(y, x); }
 
-// |N - N_exact| <= ~10 eps |c| |B - A||C - A|; 32 eps leaves margin.
-constexpr double kGuard = 32.0 * 1.1102230246251565e-16;
-
 // One strip step: triangle (O, N, Z), Z and the normal in q; Z goes to the
 // free slot F.  Returns atan2(N, D).
 __device__ __forceinline__ double step(const Vtx &O, const Vtx &Nv, Vtx &F, double &e01,
@@ -139,7 +136,7 @@ __device__ __forceinline__ double step(const Vtx &O, const Vtx &Nv, Vtx &F, doub
     double num = fma(x2, q.v[3], fma(y2, q.v[4], z2 * q.v[5]));
     const double den = fma(e12, O.r, fma(e02, Nv.r, fma(e01, r2, rr01 * r2)));
     double half;
-    if (fabs(num) <= kGuard * r2 * q.v[6]) {
+    if (fabs(num) <= r2 * q.v[6]) {   // v[6] = 32 eps |B - A||C - A| (kGuardEps)
         const ExactN x = exact_step(fx, fy, fz, head, t, num);
         num = x.n;
         if (x.flags & 2) on = 1;

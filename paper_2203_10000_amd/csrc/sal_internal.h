@@ -34,13 +34,17 @@ struct alignas(32) Rec32 {
 
 // float64 stream, same record order, 64 bytes per record:
 //   head: { x0, y0, z0, x1, y1, z1, bits(m), 0 }
-//   tri : { x, y, z,  nx, ny, nz,  |B - A| |C - A|,  sigma }
+//   tri : { x, y, z,  nx, ny, nz,  32 eps |B - A| |C - A| (enlarged),  sigma }
 // sigma = +1 when the strip order (v_i, v_{i+1}, v_{i+2}) is an even
 // permutation of (A, B, C), -1 otherwise; it orients the exact predicate.
 struct alignas(64) Rec64 {
     double v[8];
 };
 
+// |N - N_exact| <= ~10 eps |c| |B - A||C - A| for the double triple product
+// N = (Z - p) . n; the FP64 records store 32 eps |B - A||C - A| (32 eps =
+// 2^-48, margin included) so the guard is one product: |N| <= |c| v[6].
+constexpr double kGuardEps = 32.0 * 1.1102230246251565e-16;
 constexpr float kNScale = 32.0f;     // normal pre-scale in the float32 stream (a power of two)
 constexpr float kKnSmall = 5.0f;     // small-angle path needs D > 5 |n| r_Z + ...
 constexpr int kMaxSurfaces = 64;     // per-point masks are 64-bit

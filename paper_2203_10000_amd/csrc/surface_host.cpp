@@ -344,7 +344,9 @@ sal_status build_surface_records(const sal_surface_desc *desc, int32_t n, uint32
                 }
                 q32.v[6] = (float)nlen;
                 q32.v[7] = (float)(kKnSmall * nlen);
-                q64.v[6] = nb * (1.0 + 1e-12);
+                // the exact-sign guard's bound factor: 32 eps |B - A||C - A| (a
+                // power-of-two scaling, so exact), slightly enlarged
+                q64.v[6] = kGuardEps * (nb * (1.0 + 1e-12));
                 q64.v[7] = parity(f, s.verts[t], s.verts[t + 1], s.verts[t + 2]);
                 r32.push_back(q32);
                 r64.push_back(q64);

@@ -93,8 +93,9 @@ __device__ __forceinline__ double f64_strip_tri(StripF64 &s, const double *t, co
     double num = dx2 * t[3] + dy2 * t[4] + dz2 * t[5];
     const double den = s.rr01 * r2 + s.e01 * r2 + e02 * s.r1 + e12 * s.r0;
     double half = 0.0;
-    // |N - N_exact| <= ~10 eps |Z - p| |B - A| |C - A|; 32 eps leaves margin.
-    if (fabs(num) <= 32.0 * 1.1102230246251565e-16 * r2 * t[6]) {
+    // |N - N_exact| <= ~10 eps |Z - p| |B - A| |C - A|; the record holds
+    // 32 eps |B - A||C - A| (margin included).
+    if (fabs(num) <= r2 * t[6]) {
         const ExactN r = f64_exact_n(praw[0], praw[1], praw[2], s.X[0], s.X[1], s.X[2], s.Y[0], s.Y[1],
                                      s.Y[2], (float)t[0], (float)t[1], (float)t[2], t[7], num);
         num = r.n;
