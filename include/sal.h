@@ -351,6 +351,24 @@ sal_status sal_tet_mesh_size(const sal_tet_mesh *mesh, int64_t *n_leaves, int32_
 sal_status sal_tet_mesh_export(sal_context *ctx, const sal_tet_mesh *mesh, uint64_t *keys,
                                int32_t *labels, float *cx, float *cy, float *cz);
 
+/* Checkpoint / resume: rebuilds the leaves of a refined mesh from the keys
+ * and labels sal_tet_mesh_export wrote (in any order), so that refinement can
+ * continue in another process or after the original mesh is gone.  The mesh
+ * must come fresh from sal_tet_mesh_create_lattice with the same origin, h
+ * and cells.
+ *   keys, labels  device [n_leaves] (caller-owned; copied, not kept)
+ * The leaves must be exactly a nested red refinement of the lattice: every
+ * key inside the lattice and at most 3 levels deep, no key twice, every
+ * refined tetrahedron with all 8 children present (as leaves or refined), no
+ * tetrahedron both a leaf and refined, every lattice tetrahedron covered;
+ * labels >= 0.  Otherwise SAL_ERR_INVALID_ARG and the mesh is unchanged.
+ * The imported mesh is labeled under the centroid rule (the four-node rule's
+ * node table is not part of a checkpoint).  The layout of the levels may
+ * differ from the exporting mesh's; the leaves, their labels and every later
+ * refinement are the same. */
+sal_status sal_tet_mesh_import(sal_context *ctx, sal_tet_mesh *mesh, int64_t n_leaves,
+                               const uint64_t *keys, const int32_t *labels);
+
 /* ---------------------------------------------- conforming transition mesh */
 typedef struct sal_conform_info {
     int64_t n_tets;           /* tetrahedra of the conforming mesh */

@@ -162,6 +162,7 @@ _SIGNATURES = [
     ("sal_tet_mesh_size", ctypes.c_int,
      [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     ("sal_tet_mesh_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("sal_tet_mesh_import", ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     ("sal_tet_mesh_conform", ctypes.c_int, [_P, _P, ctypes.POINTER(ConformInfo)]),
     ("sal_tet_mesh_export_conforming", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("sal_smooth_params_default", None, [ctypes.POINTER(SmoothParams)]),
@@ -424,6 +425,12 @@ class TetMesh:
             _ptr(cen[0] if cen is not None else None), _ptr(cen[1] if cen is not None else None),
             _ptr(cen[2] if cen is not None else None)))
         return out
+
+    def import_leaves(self, keys, labels):
+        """sal_tet_mesh_import: keys int64/uint64 and labels int32 device tensors [n]."""
+        assert keys.is_cuda and labels.is_cuda and keys.numel() == labels.numel()
+        _check(lib().sal_tet_mesh_import(self.ctx.handle, self.handle, keys.numel(),
+                                         _ptr(keys.contiguous()), _ptr(labels.contiguous())))
 
     def conform(self):
         """sal_tet_mesh_conform: the conforming transition mesh; returns its info."""

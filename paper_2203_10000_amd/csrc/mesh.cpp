@@ -1,6 +1,7 @@
 // Tetrahedral mesh: Kuhn lattice creation, recursive refine-and-relabel
 // rounds (paper section 2.1.3 item 2), export of the leaves.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -1185,6 +1186,183 @@ sal_status sal_tet_mesh_export_conforming(sal_context *ctx, const sal_tet_mesh *
         SAL_HIP(hipMemcpyAsync(node_keys, m->conf_keys, (size_t)m->conf_nodes * sizeof(int64_t),
                                hipMemcpyDeviceToDevice, s));
     return SAL_OK;
+}
+
+namespace {
+
+struct KeyParts {
+    int l, q;
+    int64_t c[3];
+};
+
+KeyParts decode_key(uint64_t k) {
+    KeyParts p;
+    p.l = (int)(k >> 60);
+    p.q = (int)((k >> 57) & 7u);
+    p.c[0] = (int64_t)((k >> 38) & 0x7ffffu);
+    p.c[1] = (int64_t)((k >> 19) & 0x7ffffu);
+    p.c[2] = (int64_t)(k & 0x7ffffu);
+    return p;
+}
+
+uint64_t encode_key(int l, int q, const int64_t c[3]) {
+    return ((uint64_t)l << 60) | ((uint64_t)q << 57) | ((uint64_t)c[0] << 38) |
+           ((uint64_t)c[1] << 19) | (uint64_t)c[2];
+}
+
+// The parent of a level-l (l >= 1) tetrahedron and the child's rank in the
+// parent's block (the order the splits use).
+uint64_t parent_of(const sal::ChildTables &T, const KeyParts &p, int *rank) {
+    const int code = (int)(p.c[0] & 1) | (int)((p.c[1] & 1) << 1) | (int)((p.c[2] & 1) << 2);
+    const int64_t pc[3] = {p.c[0] >> 1, p.c[1] >> 1, p.c[2] >> 1};
+    for (int pq = 0; pq < 6; ++pq)
+        if (T.rank[pq][code][p.q] >= 0) {
+            *rank = T.rank[pq][code][p.q];
+            return encode_key(p.l - 1, pq, pc);
+        }
+    *rank = -1;
+    return ~0ull;
+}
+
+bool sorted_has(const std::vector<uint64_t> &v, uint64_t k) {
+    return std::binary_search(v.begin(), v.end(), k);
+}
+
+}  // namespace
+
+sal_status sal_tet_mesh_import(sal_context *ctx, sal_tet_mesh *m, int64_t n, const uint64_t *keys,
+                               const int32_t *labels) {
+    try {
+        if (!ctx || !m) return set_error(SAL_ERR_INVALID_ARG, "NULL argument");
+        if (m->device != ctx->device) return set_error(SAL_ERR_INVALID_ARG, "mesh lives on another device");
+        if (m->labeled0 || m->max_level != 0 || m->conformed)
+            return set_error(SAL_ERR_INVALID_ARG, "import needs a mesh fresh from sal_tet_mesh_create_lattice");
+        if (n <= 0 || !keys || !labels) return set_error(SAL_ERR_INVALID_ARG, "no leaves to import");
+        SAL_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = ctx->stream;
+        std::vector<uint64_t> hk((size_t)n);
+        std::vector<int32_t> hl((size_t)n);
+        SAL_HIP(hipMemcpyAsync(hk.data(), keys, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipMemcpyAsync(hl.data(), labels, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SAL_HIP(hipStreamSynchronize(s));
+        const int64_t n0 = m->n[0];
+        // leaves per level, sorted by key (label alongside)
+        std::vector<std::pair<uint64_t, int32_t>> leaf[kMaxLevels + 1];
+        for (int64_t i = 0; i < n; ++i) {
+            const KeyParts p = decode_key(hk[(size_t)i]);
+            if (p.l > kMaxLevels || p.q > 5)
+                return set_error(SAL_ERR_INVALID_ARG, "a key has no valid level or permutation");
+            for (int a = 0; a < 3; ++a)
+                if (p.c[a] >= ((int64_t)m->g.cells[a] << p.l))
+                    return set_error(SAL_ERR_INVALID_ARG, "a key lies outside the lattice");
+            if (hl[(size_t)i] < 0) return set_error(SAL_ERR_INVALID_ARG, "a leaf has no label");
+            leaf[p.l].push_back({hk[(size_t)i], hl[(size_t)i]});
+        }
+        std::vector<uint64_t> leaf_keys[kMaxLevels + 1], inner[kMaxLevels + 1];
+        for (int l = 0; l <= kMaxLevels; ++l) {
+            std::sort(leaf[l].begin(), leaf[l].end());
+            leaf_keys[l].resize(leaf[l].size());
+            for (size_t i = 0; i < leaf[l].size(); ++i) leaf_keys[l][i] = leaf[l][i].first;
+            if (std::adjacent_find(leaf_keys[l].begin(), leaf_keys[l].end()) != leaf_keys[l].end())
+                return set_error(SAL_ERR_INVALID_ARG, "a key is listed twice");
+        }
+        // inner tetrahedra: the parents of every entry one level down; each
+        // must have all 8 children and must not be a leaf itself
+        int deepest = 0;
+        for (int l = kMaxLevels; l >= 1; --l) {
+            std::vector<uint64_t> entries(leaf_keys[l]);
+            entries.insert(entries.end(), inner[l].begin(), inner[l].end());
+            if (!entries.empty()) deepest = std::max(deepest, l);
+            std::vector<uint64_t> par;
+            par.reserve(entries.size());
+            for (uint64_t k : entries) {
+                int r;
+                par.push_back(parent_of(m->T, decode_key(k), &r));
+            }
+            std::sort(par.begin(), par.end());
+            for (size_t i = 0; i < par.size();) {
+                size_t j = i;
+                while (j < par.size() && par[j] == par[i]) ++j;
+                if (j - i != 8)
+                    return set_error(SAL_ERR_INVALID_ARG, "a refined tetrahedron lacks some of its 8 children");
+                inner[l - 1].push_back(par[i]);
+                i = j;
+            }
+            for (uint64_t k : inner[l - 1])
+                if (sorted_has(leaf_keys[l - 1], k))
+                    return set_error(SAL_ERR_INVALID_ARG, "a tetrahedron is both a leaf and refined");
+        }
+        if ((int64_t)(leaf_keys[0].size() + inner[0].size()) != n0)
+            return set_error(SAL_ERR_INVALID_ARG, "the leaves do not cover the lattice");
+        // layout: level 0 by index; each refined entry's children form one
+        // block of 8 on the next level, blocks in the order of their parents
+        std::vector<uint64_t> key_l[kMaxLevels + 1];
+        std::vector<int32_t> lab_l[kMaxLevels + 1], child_l[kMaxLevels + 1];
+        lab_l[0].assign((size_t)n0, -2);
+        child_l[0].assign((size_t)n0, -1);
+        for (const auto &e : leaf[0]) {
+            const KeyParts p = decode_key(e.first);
+            const int64_t idx = ((p.c[2] * m->g.cells[1] + p.c[1]) * m->g.cells[0] + p.c[0]) * 6 + p.q;
+            lab_l[0][(size_t)idx] = e.second;
+        }
+        auto key_at = [&](int l, int64_t i) -> uint64_t {
+            if (l > 0) return key_l[l][(size_t)i];
+            const int q = (int)(i % 6);
+            int64_t cell = i / 6;
+            const int64_t c[3] = {cell % m->g.cells[0], (cell / m->g.cells[0]) % m->g.cells[1],
+                                  cell / ((int64_t)m->g.cells[0] * m->g.cells[1])};
+            return encode_key(0, q, c);
+        };
+        for (int l = 0; l < deepest; ++l) {
+            const int64_t nl = l == 0 ? n0 : (int64_t)key_l[l].size();
+            int32_t blocks = 0;
+            for (int64_t i = 0; i < nl; ++i) {
+                const uint64_t k = key_at(l, i);
+                if (!sorted_has(inner[l], k)) continue;
+                const KeyParts p = decode_key(k);
+                child_l[l][(size_t)i] = blocks;
+                for (int r = 0; r < 8; ++r) {
+                    const int code = m->T.list[p.q][r][0], cq = m->T.list[p.q][r][1];
+                    const int64_t cc[3] = {2 * p.c[0] + (code & 1), 2 * p.c[1] + ((code >> 1) & 1),
+                                           2 * p.c[2] + ((code >> 2) & 1)};
+                    const uint64_t ck = encode_key(l + 1, cq, cc);
+                    key_l[l + 1].push_back(ck);
+                    child_l[l + 1].push_back(-1);
+                    auto it = std::lower_bound(leaf[l + 1].begin(), leaf[l + 1].end(),
+                                               std::make_pair(ck, INT32_MIN));
+                    lab_l[l + 1].push_back(it != leaf[l + 1].end() && it->first == ck ? it->second : -2);
+                }
+                ++blocks;
+            }
+        }
+        // upload (everything is allocated before the mesh changes)
+        for (int l = 1; l <= deepest; ++l) {
+            sal_status st = ensure_level(m, l, (int64_t)key_l[l].size(), s);
+            if (st != SAL_OK) return st;
+        }
+        for (int l = 0; l <= deepest; ++l) {
+            const int64_t nl = l == 0 ? n0 : (int64_t)key_l[l].size();
+            if (l > 0)
+                SAL_HIP(hipMemcpyAsync(m->key[l], key_l[l].data(), (size_t)nl * sizeof(uint64_t),
+                                       hipMemcpyHostToDevice, s));
+            SAL_HIP(hipMemcpyAsync(m->label[l], lab_l[l].data(), (size_t)nl * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, s));
+            SAL_HIP(hipMemcpyAsync(m->child[l], child_l[l].data(), (size_t)nl * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, s));
+            SAL_HIP(launch_fill_u8(m->flag[l], 0, nl, s));
+        }
+        SAL_HIP(hipStreamSynchronize(s));
+        for (int l = 1; l <= deepest; ++l) m->n[l] = (int64_t)key_l[l].size();
+        m->max_level = deepest;
+        m->n_leaves = n;
+        m->rule = SAL_RULE_CENTROID;
+        m->labeled0 = true;
+        return SAL_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(SAL_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return set_error(SAL_ERR_INTERNAL, "exception in sal_tet_mesh_import");
+    }
 }
 
 sal_status sal_tet_mesh_export(sal_context *ctx, const sal_tet_mesh *mc, uint64_t *keys,
