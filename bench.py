@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--cull", action="store_true",
                     help="c3: label with bounding-box culling (pairs/s then counts the skipped "
                          "pairs as well: an effective rate)")
+    ap.add_argument("--converge", action="store_true",
+                    help="c3: the recursion until the label boundary stops changing "
+                         "(finest level = the config's rounds) instead of fixed rounds")
     ap.add_argument("--fp64-round0", action="store_true",
                     help="c3: also time the plain FP64 form on round 0 (the whole lattice)")
     ap.add_argument("--no-c3-leg", action="store_true",
@@ -351,7 +354,12 @@ def run_c3(args, fp64_sample=True):
     mesh = sal.TetMesh(ctx, lat.origin, lat.h, lat.cells)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = mesh.refine_relabel(ss, cfg.rounds, precision="fp32", rule=args.rule, cull=args.cull)
+    converged = None
+    if getattr(args, "converge", False):
+        st, converged = mesh.refine_converge(ss, cfg.rounds, max_steps=32, precision="fp32",
+                                             rule=args.rule, cull=args.cull)
+    else:
+        st = mesh.refine_relabel(ss, cfg.rounds, precision="fp32", rule=args.rule, cull=args.cull)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pairs = sum(r["n_pairs"] for r in st)
@@ -379,6 +387,8 @@ def run_c3(args, fp64_sample=True):
         else:
             mism, checked = _oracle_check(cen, cfg.surfaces, lab, args.check_sample, rng, near)
     out = {"workload": "c3", "rule": args.rule, "cull_bounds": bool(args.cull),
+           "recursion": "converging" if converged is not None else "fixed rounds",
+           "converged": converged,
            "triangles": cfg.n_tri, "rounds": st, "leaves": n_leaves, "max_level": lv,
            "pairs": pairs, "wall_s": wall, "g_pairs_per_s": pairs / wall / 1e9,
            "pairloop_ms": ms_label,
