@@ -17,7 +17,7 @@
 //    (the point is a vertex) gives exactly 0 instead of 0 * inf.  Any s > 0
 //    here is at least ~1e-90 (a squared difference of two float32 values),
 //    far inside the normal range, so no scaling is needed;
-//  * N / D in the small-angle path (only taken when D > 16 |N| > 0) from
+//  * N / D in the small-angle path (only taken when D > 512 |N| > 0) from
 //    the hardware reciprocal, one Newton step and a residual correction.
 // Both are within a few units in the last place of the correctly rounded
 // results; they only enter magnitudes (|c| and the angle of a far triangle),
@@ -118,8 +118,8 @@ __device__ __noinline__ ExactN exact_step(float px, float py, float pz, const Re
     return r;
 }
 
-// The library atan2 for the near triangles (|N / D| >= 1/16, a few per point
-// near a surface).  Out of line: inlined, its polynomial constants were
+// The library atan2 for the near triangles (|N / D| >= 1/512: for a triangle
+// with legs h, within about 11 h of the point).  Out of line: inlined, its polynomial constants were
 // hoisted out of the loop into some forty registers, which spilled.
 __device__ __noinline__ double atan2_ool(double y, double x) { return atan2(y, x); }
 
@@ -142,16 +142,14 @@ __device__ __forceinline__ double step(const Vtx &O, const Vtx &Nv, Vtx &F, doub
         if (x.flags & 2) on = 1;
         n_exact += 1;
         half = (x.flags & 1) ? 0.0 : atan2_ool(num, den);
-    } else if (den > 16.0 * fabs(num)) {
-        // |N / D| < 1/16, D > 0: atan(t) by its Taylor series to t^13 (the
-        // first omitted term is below 1e-18 t)
+    } else if (den > 512.0 * fabs(num)) {
+        // |N / D| < 1/512, D > 0: atan(t) by its Taylor series to t^5 (the
+        // first omitted term, t^7 / 7, is below 8e-18 t).  Wider ranges need
+        // more terms and ran slower: 1/128 with terms to t^7 by 2 %, 1/16
+        // with terms to t^13 by 12 %; the atan2 calls of the few extra near
+        // triangles cost less than a longer polynomial on every far one.
         const double tt = div_pos(num, den), s = tt * tt;
-        double poly = 1.0 / 13.0;
-        poly = fma(poly, s, -1.0 / 11.0);
-        poly = fma(poly, s, 1.0 / 9.0);
-        poly = fma(poly, s, -1.0 / 7.0);
-        poly = fma(poly, s, 1.0 / 5.0);
-        poly = fma(poly, s, -1.0 / 3.0);
+        const double poly = fma(1.0 / 5.0, s, -1.0 / 3.0);
         half = fma(tt * s, poly, tt);
     } else {
         half = atan2_ool(num, den);
