@@ -5,15 +5,15 @@
 // c = Z - p, the half solid angle is atan2(N, D), N = c . n (n the outward
 // normal (B - A) x (C - A) of the original triangle, from the record),
 // D = |a||b||c| + (a.b)|c| + (a.c)|b| + (b.c)|a|.  The per-vertex length and
-// the per-edge dot product carry over to the next step, and three vertex
+// the per-edge term |a||b| + a.b carry over to the next step, and three vertex
 // slots rotate (the loop is unrolled by three), so nothing is copied.
 //
 // Where the float32 walk is issue-bound on plain ALU work, this one was bound
 // by its library calls: a correctly rounded double sqrt and a double division
 // each expand to about a dozen instructions with scaling and special-case
 // fix-ups that these operands never need.  Here:
-//  * |c| = sqrt(s) from the hardware reciprocal square root and Newton
-//    steps (Goldschmidt form), with s >= 1e-200 forced first so that s = 0
+//  * |c| = sqrt(s) from the hardware reciprocal square root, one
+//    Goldschmidt step and a residual correction, with s >= 1e-200 forced first so that s = 0
 //    (the point is a vertex) gives exactly 0 instead of 0 * inf.  Any s > 0
 //    here is at least ~1e-90 (a squared difference of two float32 values),
 //    far inside the normal range, so no scaling is needed;
@@ -57,15 +57,16 @@ __device__ __forceinline__ Rec load_rec(const CRec64 *p) {
 }
 
 // sqrt(s) for s = 0 or s >= ~1e-90: y ~ 1/sqrt(s), g = s y, h = y / 2, one
-// Goldschmidt step on (g, h), then the residual correction g += (s - g^2) h.
+// Goldschmidt step on g, then the residual correction g += (s - g^2) h.  The
+// correction is ~2^-48 g, so h needs only the estimate's ~24 bits: the
+// Goldschmidt update of h is left out (no change in the result beyond an
+// occasional last-place unit).
 __device__ __forceinline__ double sqrt_nn(double s) {
     const double sm = fmax(s, 1e-200);
     const double y = __builtin_amdgcn_rsq(sm);
     double g = s * y;
-    double h = 0.5 * y;
-    const double e = fma(-g, h, 0.5);
-    g = fma(g, e, g);
-    h = fma(h, e, h);
+    const double h = 0.5 * y;
+    g = fma(g, fma(-g, h, 0.5), g);
     const double d = fma(-g, g, s);
     return fma(d, h, g);
 }
@@ -125,8 +126,8 @@ __device__ __noinline__ double atan2_ool(double y, double x) { return atan2(y, x
 
 // One strip step: triangle (O, N, Z), Z and the normal in q; Z goes to the
 // free slot F.  Returns atan2(N, D).
-__device__ __forceinline__ double step(const Vtx &O, const Vtx &Nv, Vtx &F, double &e01,
-                                       double &rr01, const Rec &q, double px, double py,
+__device__ __forceinline__ double step(const Vtx &O, const Vtx &Nv, Vtx &F, double &kab,
+                                       const Rec &q, double px, double py,
                                        double pz, float fx, float fy, float fz,
                                        const Rec64 *head, int t, int &on, unsigned &n_exact) {
     const double x2 = q.v[0] - px, y2 = q.v[1] - py, z2 = q.v[2] - pz;
@@ -134,7 +135,9 @@ __device__ __forceinline__ double step(const Vtx &O, const Vtx &Nv, Vtx &F, doub
     const double e02 = fma(O.x, x2, fma(O.y, y2, O.z * z2));
     const double e12 = fma(Nv.x, x2, fma(Nv.y, y2, Nv.z * z2));
     double num = fma(x2, q.v[3], fma(y2, q.v[4], z2 * q.v[5]));
-    const double den = fma(e12, O.r, fma(e02, Nv.r, fma(e01, r2, rr01 * r2)));
+    // D = |c| (|a||b| + a.b) + (a.c)|b| + (b.c)|a|; kab = |a||b| + a.b carries
+    // over from the previous step
+    const double den = fma(r2, kab, fma(e02, Nv.r, e12 * O.r));
     double half;
     if (fabs(num) <= r2 * q.v[6]) {   // v[6] = 32 eps |B - A||C - A| (kGuardEps)
         const ExactN x = exact_step(fx, fy, fz, head, t, num);
@@ -154,8 +157,7 @@ __device__ __forceinline__ double step(const Vtx &O, const Vtx &Nv, Vtx &F, doub
     } else {
         half = atan2_ool(num, den);
     }
-    rr01 = Nv.r * r2;
-    e01 = e12;
+    kab = fma(Nv.r, r2, e12);
     F.x = x2;
     F.y = y2;
     F.z = z2;
@@ -178,8 +180,7 @@ __device__ __forceinline__ double surface_sum(const CRec64 *rec, int64_t rec_beg
         B.x = hd.v[3] - px; B.y = hd.v[4] - py; B.z = hd.v[5] - pz;
         A.r = sqrt_nn(fma(A.x, A.x, fma(A.y, A.y, A.z * A.z)));
         B.r = sqrt_nn(fma(B.x, B.x, fma(B.y, B.y, B.z * B.z)));
-        double e01 = fma(A.x, B.x, fma(A.y, B.y, A.z * B.z));
-        double rr01 = A.r * B.r;
+        double kab = fma(A.r, B.r, fma(A.x, B.x, fma(A.y, B.y, A.z * B.z)));
         double acc = 0.0;
         // records prefetched one step ahead, as in the float32 walk
         const CRec64 *tr = rec + r + 1;
@@ -190,22 +191,22 @@ __device__ __forceinline__ double surface_sum(const CRec64 *rec, int64_t rec_beg
             __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
             c1 = load_rec(tr + (t + 1));
             __builtin_amdgcn_sched_barrier(0);
-            acc += step(A, B, C, e01, rr01, c0, px, py, pz, fx, fy, fz, head, t + 1, on, n_exact);
+            acc += step(A, B, C, kab, c0, px, py, pz, fx, fy, fz, head, t + 1, on, n_exact);
             __builtin_amdgcn_s_waitcnt(0xc07f);
             c2 = load_rec(tr + (t + 2));
             __builtin_amdgcn_sched_barrier(0);
-            acc += step(B, C, A, e01, rr01, c1, px, py, pz, fx, fy, fz, head, t + 2, on, n_exact);
+            acc += step(B, C, A, kab, c1, px, py, pz, fx, fy, fz, head, t + 2, on, n_exact);
             __builtin_amdgcn_s_waitcnt(0xc07f);
             c0 = load_rec(tr + (t + 3 < last ? t + 3 : last));
             __builtin_amdgcn_sched_barrier(0);
-            acc += step(C, A, B, e01, rr01, c2, px, py, pz, fx, fy, fz, head, t + 3, on, n_exact);
+            acc += step(C, A, B, kab, c2, px, py, pz, fx, fy, fz, head, t + 3, on, n_exact);
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);
         if (t < m) {
-            acc += step(A, B, C, e01, rr01, c0, px, py, pz, fx, fy, fz, head, t + 1, on, n_exact);
+            acc += step(A, B, C, kab, c0, px, py, pz, fx, fy, fz, head, t + 1, on, n_exact);
             if (t + 1 < m) {
                 c1 = load_rec(tr + (t + 1));
-                acc += step(B, C, A, e01, rr01, c1, px, py, pz, fx, fy, fz, head, t + 2, on,
+                acc += step(B, C, A, kab, c1, px, py, pz, fx, fy, fz, head, t + 2, on,
                             n_exact);
             }
         }
