@@ -492,8 +492,10 @@ sal_status sal_tet_mesh_inflate(sal_context *ctx, sal_tet_mesh *mesh, const sal_
  * cut into (instance, point block, surface, triangle range) items ordered by
  * cost, pulled by resident workgroups from a device counter; partial winding
  * sums are reduced per (point, surface) in a fixed order; one FP64 recheck
- * pass serves all instances.  Labels equal those of sal_label_points on each
- * instance.  Each instance's arrays follow the rules of sal_label_points.
+ * pass serves all instances.  With precision SAL_PREC_FP64 the items run the
+ * plain FP64 walk (exact sign where double cannot certify it, points on a
+ * surface enclosed) and there is no recheck.  Labels equal those of
+ * sal_label_points on each instance.  Each instance's arrays follow the rules of sal_label_points.
  *   per_instance  NULL, or [n_inst] stats filled after synchronising */
 typedef struct sal_instance {
     const sal_surface_set *surfaces;

@@ -83,18 +83,7 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
         SAL_HIP(hipSetDevice(ctx->device));
         hipStream_t s = ctx->stream;
 
-        if (opt.precision == SAL_PREC_FP64) {
-            // the plain FP64 form has no float32 pass to batch: one launch per instance
-            for (int i = 0; i < n_inst; ++i) {
-                sal_label_stats one;
-                st = sal_label_points(ctx, inst[i].surfaces, inst[i].n_points, inst[i].x, inst[i].y,
-                                      inst[i].z, &opt, inst[i].labels, nullptr,
-                                      stats ? &one : nullptr);
-                if (st != SAL_OK) return st;
-                if (stats) stats[i] = one;
-            }
-            return SAL_OK;
-        }
+        const bool fp64 = opt.precision == SAL_PREC_FP64;
 
         // cache key of this batch (graph replay)
         uint64_t key = 0x51ed270b2717ull;
@@ -115,6 +104,7 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
         std::memcpy(&kb, &opt.recheck_band, 8);
         key = mix(key, kb);
         key = mix(key, (uint64_t)n_inst);
+        key = mix(key, fp64 ? 2u : 1u);
 
         st = ensure_flag_capacity(ctx, total);
         if (st != SAL_OK) return st;
@@ -235,7 +225,10 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
         a.flag_list = ctx->flag_list;
         a.counters = ctx->counters;
         a.inst_counters = ctx->batch_counters;
-        const int pblocks = ctx->n_cu * 8;
+        a.fp64 = fp64 ? 1 : 0;
+        // workgroups of 4 wavefronts that fill the chip once: 8 wavefronts per
+        // SIMD for the float32 kernel, 4 for the FP64 one
+        const int pblocks = ctx->n_cu * (fp64 ? 4 : 8);
         const int rblocks = (int)std::min<int64_t>(total, (int64_t)ctx->n_cu * 8);
 
         auto enqueue = [&](hipStream_t q) -> sal_status {

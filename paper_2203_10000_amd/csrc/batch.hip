@@ -5,13 +5,15 @@
 // ordered by cost, largest first, and every resident wavefront pulls the next
 // item from a device counter until the list is exhausted (every wavefront
 // exits when the counter passes the item count).  An item writes its 64
-// float64 partial sums and its conditioning mask to a slot; the finalize pass
-// adds the slots of each (point, surface) in split order, so results do not
-// depend on which wavefront ran what.
+// float64 partial sums and a 64-bit lane mask to a slot (float32 form: the
+// conditioning flags; plain FP64 form: the points found on the surface); the
+// finalize pass adds the slots of each (point, surface) in split order, so
+// results do not depend on which wavefront ran what.
 #include <hip/hip_runtime.h>
 
 #include "batch_internal.h"
 #include "pairloop_f32.h"
+#include "pairloop_f64.h"
 #include "recheck_mixed.h"
 #include "vos_f64.h"
 
@@ -57,6 +59,40 @@ __global__ __launch_bounds__(256) void k_batch_pairloop(BatchArgs a) {
     }
 }
 
+// The plain FP64 form of the same work list: every pair in double with the
+// exact sign where double cannot certify it (the per-point FP64 walk), no
+// float32 pass and so no recheck.  Occupancy as the per-point FP64 kernel.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_pairloop_f64(
+    BatchArgs a) {
+    const CItem *items = (const CItem *)a.items;
+    const CInst *insts = (const CInst *)a.insts;
+    const int lane = lane_id();
+    for (;;) {
+        // claim as in the float32 kernel: every lane executes the atomic
+        const unsigned int got = atomicAdd(a.next_item, lane == 0 ? 1u : 0u);
+        const unsigned int it = (unsigned int)__builtin_amdgcn_readfirstlane((int)got);
+        if ((int64_t)it >= a.n_items) break;
+        const CItem *item = items + it;
+        const CInst *inst = insts + item->inst;
+        const int64_t p = item->block * 64 + lane;
+        const bool valid = p < inst->n;
+        float fx = valid ? inst->x[p] : 0.0f, fy = valid ? inst->y[p] : 0.0f,
+              fz = valid ? inst->z[p] : 0.0f;
+        const bool good = valid && finite3(fx, fy, fz);
+        if (!good) { fx = 0.0f; fy = 0.0f; fz = 0.0f; }
+        int on = 0;
+        unsigned n_exact = 0;
+        const double S = f64::surface_sum((const CRec64 *)inst->rec64, item->rec_begin,
+                                          item->rec_end, fx, fy, fz, fx, fy, fz, on, n_exact);
+        a.partial[item->slot * 64 + lane] = S;
+        const uint64_t on_mask = ballot(on != 0 && good);
+        if (lane == 0) a.slot_mask[item->slot] = on_mask;
+        if (n_exact && good)
+            atomicAdd(&a.inst_counters[(int64_t)item->inst * kNumCounters + kCntExact],
+                      (unsigned long long)n_exact);
+    }
+}
+
 __device__ __forceinline__ int find_inst(const BatchInst *insts, int n_inst, int64_t gp) {
     int lo = 0, hi = n_inst - 1;
     while (lo < hi) {
@@ -68,7 +104,9 @@ __device__ __forceinline__ int find_inst(const BatchInst *insts, int n_inst, int
 }
 
 // Per point: winding numbers from the partial slots, the label decision of
-// section 2.1.3 (s >= T, later surface wins) and the recheck flags.
+// section 2.1.3 (s >= T, later surface wins) and the recheck flags.  In the
+// plain FP64 form the slot masks mark points on the surface (enclosed) and
+// nothing is flagged.
 __global__ __launch_bounds__(256) void k_batch_finalize(BatchArgs a) {
     const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = gp < a.total_points;
@@ -87,15 +125,16 @@ __global__ __launch_bounds__(256) void k_batch_finalize(BatchArgs a) {
         unsigned n_band = 0, n_cond = 0;
         for (int k = 0; k < in.n_surf; ++k) {
             double S = 0.0;
-            bool cond = false;
+            bool bit = false;
             for (int s = in.split_off[k]; s < in.split_off[k + 1]; ++s) {
                 const int64_t slot = in.slot_base + block * in.splits_total + s;
                 S += a.partial[slot * 64 + ln];
-                cond |= ((a.slot_mask[slot] >> ln) & 1ull) != 0;
+                bit |= ((a.slot_mask[slot] >> ln) & 1ull) != 0;
             }
             const double w = S * kInv2Pi;
-            const bool inside = w >= a.threshold;
-            const bool band = fabs(w - a.threshold) < a.band;
+            const bool inside = (a.fp64 && bit) || w >= a.threshold;
+            const bool band = !a.fp64 && fabs(w - a.threshold) < a.band;
+            const bool cond = !a.fp64 && bit;
             if (inside) { enc |= 1ull << k; lab = in.surf_label[k]; }
             if (band || cond) flg |= 1ull << k;
             n_band += band;
@@ -181,12 +220,15 @@ __global__ __launch_bounds__(kRecheckThreads) void k_batch_recheck(BatchArgs a) 
 
 hipError_t launch_batch(const BatchArgs &a, int persistent_blocks, int recheck_blocks,
                         hipStream_t s) {
-    if (a.n_items > 0)
-        k_batch_pairloop<<<dim3(persistent_blocks), dim3(256), 0, s>>>(a);
+    if (a.n_items > 0) {
+        if (a.fp64) k_batch_pairloop_f64<<<dim3(persistent_blocks), dim3(256), 0, s>>>(a);
+        else k_batch_pairloop<<<dim3(persistent_blocks), dim3(256), 0, s>>>(a);
+    }
     if (a.total_points > 0) {
         const int64_t g = (a.total_points + 255) / 256;
         k_batch_finalize<<<dim3((unsigned)g), dim3(256), 0, s>>>(a);
-        k_batch_recheck<<<dim3(recheck_blocks), dim3(kRecheckThreads), 0, s>>>(a);
+        if (!a.fp64)
+            k_batch_recheck<<<dim3(recheck_blocks), dim3(kRecheckThreads), 0, s>>>(a);
     }
     return hipGetLastError();
 }

@@ -39,12 +39,14 @@ struct BatchArgs {
     int64_t total_points;
     unsigned int *next_item;
     double *partial;        // [slots][64]
-    uint64_t *slot_mask;    // [slots]
+    uint64_t *slot_mask;    // [slots]: conditioning flags (float32 form) or
+                            // points on the surface (plain FP64 form)
     float kappa;
     double threshold, band;
     FlagEntry *flag_list;   // capacity total_points
     unsigned long long *counters;       // kCntFlagged = list length
     unsigned long long *inst_counters;  // [n_inst][kNumCounters]
+    int fp64;               // plain FP64 form: FP64 walk, no float32 pass, no recheck
 };
 
 hipError_t launch_batch(const BatchArgs &a, int persistent_blocks, int recheck_blocks,

@@ -57,7 +57,8 @@ def test_batch_equals_per_instance_and_oracle(ctx):
         assert s["n_points"] == pts.shape[1]
 
 
-def test_batch_splits_large_surfaces(ctx):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_splits_large_surfaces(ctx, precision):
     """Few points, large surfaces: the work list cuts surfaces into strip
     ranges whose partial sums are reduced in order."""
     cfg = synth.config_small("shells", subdiv=5)
@@ -65,15 +66,16 @@ def test_batch_splits_large_surfaces(ctx):
     pts = np.concatenate([synth.uniform_box(rng, 200, -100, 100),
                           synth.near_surface_points(rng, cfg.surfaces, 200, 0.5)], 1)
     dev = build(ctx, [(cfg.surfaces, pts)])
-    sal.label_batch(ctx, dev)
+    sal.label_batch(ctx, dev, precision=precision)
     torch.cuda.synchronize()
     assert np.array_equal(dev[0][2].cpu().numpy(), oracle.label(pts, cfg.surfaces))
 
 
-def test_batch_graph_replays(ctx):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_graph_replays(ctx, precision):
     insts = small_instances(4, seed=10)
     dev = build(ctx, insts)
-    sal.label_batch(ctx, dev, use_graph=True)        # capture + launch
+    sal.label_batch(ctx, dev, use_graph=True, precision=precision)   # capture + launch
     torch.cuda.synchronize()
     first = [lab.clone() for _, _, lab in dev]
     for rep in range(3):
@@ -81,7 +83,7 @@ def test_batch_graph_replays(ctx):
         for _, p, lab in dev:
             lab.fill_(-9)
         x = torch.randn(1000, device="cuda:0").sum()
-        sal.label_batch(ctx, dev, use_graph=True)    # replay
+        sal.label_batch(ctx, dev, use_graph=True, precision=precision)   # replay
         torch.cuda.synchronize()
         for f, (_, _, lab) in zip(first, dev):
             assert torch.equal(f, lab), rep
@@ -93,19 +95,33 @@ def test_batch_graph_replays(ctx):
         q = synth.uniform_box(rng, pts.shape[1], -100, 100)
         p.copy_(torch.from_numpy(q))
         new.append((surfs, q))
-    sal.label_batch(ctx, dev, use_graph=True)
+    sal.label_batch(ctx, dev, use_graph=True, precision=precision)
     torch.cuda.synchronize()
     for (surfs, q), (_, _, lab) in zip(new, dev):
         assert np.array_equal(lab.cpu().numpy(), oracle.label(q, surfs))
 
 
 def test_batch_fp64_form(ctx):
+    """The persistent FP64 kernel: labels equal the per-point FP64 form's and
+    the oracle's, points exactly on a triangle count as enclosed, and the
+    exact-sign evaluations are counted per instance."""
     insts = small_instances(3, seed=20)
+    # instance 0 also gets points exactly on its surfaces (vertices and
+    # exactly representable edge midpoints)
+    surfs0, pts0 = insts[0]
+    on = np.concatenate([synth.face_centroids_on_surface(s, 50) for s in surfs0], 1)
+    insts[0] = (surfs0, np.concatenate([pts0, on], 1))
     dev = build(ctx, insts)
-    sal.label_batch(ctx, dev, precision="fp64")
+    st = sal.label_batch(ctx, dev, precision="fp64", stats=True)
     torch.cuda.synchronize()
-    for (surfs, pts), (_, _, lab) in zip(insts, dev):
-        assert np.array_equal(lab.cpu().numpy(), oracle.label(pts, surfs))
+    for (surfs, pts), (ss, p, lab), s in zip(insts, dev, st):
+        got = lab.cpu().numpy()
+        single, _, one = sal.label_points(ctx, ss, p, precision="fp64", stats=True)
+        assert np.array_equal(got, single.cpu().numpy())
+        assert np.array_equal(got, oracle.label(pts, surfs))
+        assert s["n_exact_fallbacks"] == one["n_exact_fallbacks"]
+        assert s["n_recheck_points"] == 0
+    assert st[0]["n_exact_fallbacks"] > 0
 
 
 def test_batch_rejects_winding_and_nulls(ctx):

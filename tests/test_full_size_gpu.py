@@ -107,6 +107,19 @@ def test_c4_full_size_batched(ctx):
     for (surfs, pts), a in zip(insts, per):
         want = oracle.RadialSet(surfs).label(pts, n_threads=oracle.host_threads())
         assert np.array_equal(a.cpu().numpy(), want)
+    # the plain FP64 form: the persistent batched kernel (eager and hipGraph)
+    # equals the per-instance FP64 launches and the float32 form's labels
+    per64 = []
+    for ss, p, _ in dev:
+        lab, _, _ = sal.label_points(ctx, ss, p, precision="fp64")
+        per64.append(lab)
+    assert all(torch.equal(a, b) for a, b in zip(per, per64))
+    for graph in (False, True, True):
+        for _, _, l in dev:
+            l.fill_(-7)
+        sal.label_batch(ctx, dev, precision="fp64", use_graph=graph)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, l) for a, (_, _, l) in zip(per64, dev))
 
 
 def test_c5_surfaces_near_surface_points(ctx):
