@@ -13,10 +13,12 @@
 // each expand to about a dozen instructions with scaling and special-case
 // fix-ups that these operands never need.  Here:
 //  * |c| = sqrt(s) from the hardware reciprocal square root, one
-//    Goldschmidt step and a residual correction, with s >= 1e-200 forced first so that s = 0
-//    (the point is a vertex) gives exactly 0 instead of 0 * inf.  Any s > 0
-//    here is at least ~1e-90 (a squared difference of two float32 values),
-//    far inside the normal range, so no scaling is needed;
+//    Goldschmidt step and a residual correction.  s carries a seed of
+//    1e-200 (the innermost FMA of the sum of squares adds it), so a point on
+//    a vertex gets |c| = 1e-100 instead of 0 * inf; any nonzero sum is at
+//    least ~1e-90 (a squared difference of two float32 values), which the
+//    seed leaves unchanged, and far inside the normal range, so no scaling is
+//    needed;
 //  * N / D in the small-angle path (only taken when D > 512 |N| > 0) from
 //    the hardware reciprocal, one Newton step and a residual correction.
 // Both are within a few units in the last place of the correctly rounded
@@ -56,19 +58,24 @@ __device__ __forceinline__ Rec load_rec(const CRec64 *p) {
     return r;
 }
 
-// sqrt(s) for s = 0 or s >= ~1e-90: y ~ 1/sqrt(s), g = s y, h = y / 2, one
+// sqrt(s) for s >= 1e-200: y ~ 1/sqrt(s), g = s y, h = y / 2, one
 // Goldschmidt step on g, then the residual correction g += (s - g^2) h.  The
 // correction is ~2^-48 g, so h needs only the estimate's ~24 bits: the
 // Goldschmidt update of h is left out (no change in the result beyond an
 // occasional last-place unit).
 __device__ __forceinline__ double sqrt_nn(double s) {
-    const double sm = fmax(s, 1e-200);
-    const double y = __builtin_amdgcn_rsq(sm);
+    const double y = __builtin_amdgcn_rsq(s);
     double g = s * y;
     const double h = 0.5 * y;
     g = fma(g, fma(-g, h, 0.5), g);
     const double d = fma(-g, g, s);
     return fma(d, h, g);
+}
+
+// x^2 + y^2 + z^2 + 1e-200: the seed costs nothing (it replaces the product
+// that starts the FMA chain) and keeps the sum a valid sqrt_nn argument.
+__device__ __forceinline__ double sq_seeded(double x, double y, double z, double seed) {
+    return fma(x, x, fma(y, y, fma(z, z, seed)));
 }
 
 // num / den for den > 0 finite (both normal): reciprocal, one Newton step,
@@ -129,9 +136,10 @@ __device__ __noinline__ double atan2_ool(double y, double x) { return atan2(y, x
 __device__ __forceinline__ double step(const Vtx &O, const Vtx &Nv, Vtx &F, double &kab,
                                        const Rec &q, double px, double py,
                                        double pz, float fx, float fy, float fz,
-                                       const Rec64 *head, int t, int &on, unsigned &n_exact) {
+                                       const Rec64 *head, int t, int &on, unsigned &n_exact,
+                                       double seed) {
     const double x2 = q.v[0] - px, y2 = q.v[1] - py, z2 = q.v[2] - pz;
-    const double r2 = sqrt_nn(fma(x2, x2, fma(y2, y2, z2 * z2)));
+    const double r2 = sqrt_nn(sq_seeded(x2, y2, z2, seed));
     const double e02 = fma(O.x, x2, fma(O.y, y2, O.z * z2));
     const double e12 = fma(Nv.x, x2, fma(Nv.y, y2, Nv.z * z2));
     double num = fma(x2, q.v[3], fma(y2, q.v[4], z2 * q.v[5]));
@@ -171,6 +179,10 @@ __device__ __forceinline__ double surface_sum(const CRec64 *rec, int64_t rec_beg
                                               double px, double py, double pz, float fx, float fy,
                                               float fz, int &on, unsigned &n_exact) {
     double S = 0.0;
+    // the sum-of-squares seed, held in scalar registers (as a literal it was
+    // copied into a vector register before every use)
+    double seed = 1e-200;
+    asm("" : "+s"(seed));
     for (int64_t r = rec_begin; r < rec_end;) {
         const Rec hd = load_rec(rec + r);
         const int m = (int)(__double_as_longlong(hd.v[6]) & 0x7fffffff);
@@ -178,8 +190,8 @@ __device__ __forceinline__ double surface_sum(const CRec64 *rec, int64_t rec_beg
         Vtx A, B, C;
         A.x = hd.v[0] - px; A.y = hd.v[1] - py; A.z = hd.v[2] - pz;
         B.x = hd.v[3] - px; B.y = hd.v[4] - py; B.z = hd.v[5] - pz;
-        A.r = sqrt_nn(fma(A.x, A.x, fma(A.y, A.y, A.z * A.z)));
-        B.r = sqrt_nn(fma(B.x, B.x, fma(B.y, B.y, B.z * B.z)));
+        A.r = sqrt_nn(sq_seeded(A.x, A.y, A.z, seed));
+        B.r = sqrt_nn(sq_seeded(B.x, B.y, B.z, seed));
         double kab = fma(A.r, B.r, fma(A.x, B.x, fma(A.y, B.y, A.z * B.z)));
         double acc = 0.0;
         // records prefetched one step ahead, as in the float32 walk
@@ -191,23 +203,23 @@ __device__ __forceinline__ double surface_sum(const CRec64 *rec, int64_t rec_beg
             __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
             c1 = load_rec(tr + (t + 1));
             __builtin_amdgcn_sched_barrier(0);
-            acc += step(A, B, C, kab, c0, px, py, pz, fx, fy, fz, head, t + 1, on, n_exact);
+            acc += step(A, B, C, kab, c0, px, py, pz, fx, fy, fz, head, t + 1, on, n_exact, seed);
             __builtin_amdgcn_s_waitcnt(0xc07f);
             c2 = load_rec(tr + (t + 2));
             __builtin_amdgcn_sched_barrier(0);
-            acc += step(B, C, A, kab, c1, px, py, pz, fx, fy, fz, head, t + 2, on, n_exact);
+            acc += step(B, C, A, kab, c1, px, py, pz, fx, fy, fz, head, t + 2, on, n_exact, seed);
             __builtin_amdgcn_s_waitcnt(0xc07f);
             c0 = load_rec(tr + (t + 3 < last ? t + 3 : last));
             __builtin_amdgcn_sched_barrier(0);
-            acc += step(C, A, B, kab, c2, px, py, pz, fx, fy, fz, head, t + 3, on, n_exact);
+            acc += step(C, A, B, kab, c2, px, py, pz, fx, fy, fz, head, t + 3, on, n_exact, seed);
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);
         if (t < m) {
-            acc += step(A, B, C, kab, c0, px, py, pz, fx, fy, fz, head, t + 1, on, n_exact);
+            acc += step(A, B, C, kab, c0, px, py, pz, fx, fy, fz, head, t + 1, on, n_exact, seed);
             if (t + 1 < m) {
                 c1 = load_rec(tr + (t + 1));
                 acc += step(B, C, A, kab, c1, px, py, pz, fx, fy, fz, head, t + 2, on,
-                            n_exact);
+                            n_exact, seed);
             }
         }
         S += acc;
