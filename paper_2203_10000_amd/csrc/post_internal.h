@@ -36,6 +36,8 @@ struct SmoothCache {
     int32_t *order = nullptr;    // [n_nodes] node id of each Morton rank
     int32_t *list[2] = {};       // nodes of the surface and of the volume phase
     uint64_t *seg[2] = {};       // their row segments
+    uint32_t *head[2] = {};      // the first kTaubinGroup * kTaubinUnroll columns of each
+                                 // listed row at a fixed stride (see launch_row_heads)
     int64_t n_list[2] = {};
     int64_t n_entries[2] = {};   // row entries read per half step of each phase
     float4 *pos[2] = {};         // [n_nodes] working positions (w unused)
@@ -98,11 +100,18 @@ hipError_t launch_row_entries(const int64_t *rowptr, const int32_t *list, int64_
 // over node i and its neighbours (interface edges only when surface_only);
 // *sum = sum of |out_i - in_i|^2.
 hipError_t launch_taubin_half(const float4 *in, float4 *out, const uint64_t *seg,
-                              const uint32_t *cols, const int32_t *list, int64_t n, double coef,
-                              int surface_only, double *partials, double *sum, hipStream_t s);
+                              const uint32_t *head, const uint32_t *cols, const int32_t *list,
+                              int64_t n, double coef, int surface_only, double *partials,
+                              double *sum, hipStream_t s);
 // seg[t] = (rowptr[list[t]] << 32) | row length (rows below 2^32 entries)
 hipError_t launch_row_segments(const int64_t *rowptr, const int32_t *list, int64_t n, uint64_t *seg,
                                hipStream_t s);
+// head[(t G + g) U + u] = column q = g + u G of row list[t] (0 past the row's
+// end), G = kTaubinGroup, U = kTaubinUnroll: each lane of a node's group
+// reads its first U columns as contiguous 16-byte loads, without waiting for
+// the row segment.  [n][G U] entries.
+hipError_t launch_row_heads(const int64_t *rowptr, const uint32_t *cols, const int32_t *list,
+                            int64_t n, uint32_t *head, hipStream_t s);
 // Inflation (inflate.hip): triangles of the surface set (9 floats, sorted
 // vertices), binned on the level-0 lattice.
 hipError_t launch_strip_triangles(const Rec64 *rec, const int64_t *strip_off, const int64_t *tri_base,

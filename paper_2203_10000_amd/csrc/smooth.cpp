@@ -17,6 +17,7 @@ namespace sal {
 void smooth_cache_free(SmoothCache *c) {
     if (!c) return;
     void *p[] = {c->rowptr, c->cols, c->cls, c->order, c->list[0], c->list[1], c->seg[0], c->seg[1],
+                 c->head[0], c->head[1],
                  c->pos[0], c->pos[1], c->partials, c->sum};
     for (void *q : p)
         if (q) (void)hipFree(q);
@@ -141,6 +142,9 @@ sal_status build_graph(const ConformView &v, SmoothCache *c, hipStream_t s) {
     for (int ph = 0; ph < 2; ++ph) {
         if ((st = dev_alloc(&c->seg[ph], c->n_list[ph])) != SAL_OK) return st;
         SAL_HIP(launch_row_segments(c->rowptr, c->list[ph], c->n_list[ph], c->seg[ph], s));
+        if ((st = dev_alloc(&c->head[ph], c->n_list[ph] * kTaubinGroup * kTaubinUnroll)) != SAL_OK)
+            return st;
+        SAL_HIP(launch_row_heads(c->rowptr, c->cols, c->list[ph], c->n_list[ph], c->head[ph], s));
         double e = 0.0;
         SAL_HIP(launch_row_entries(c->rowptr, c->list[ph], c->n_list[ph], c->partials, c->sum, s));
         SAL_HIP(hipMemcpyAsync(&e, c->sum, sizeof(e), hipMemcpyDeviceToHost, s));
@@ -173,11 +177,11 @@ sal_status run_phase(SmoothCache *c, int ph, double lam, double mu, double xi, i
     if ((st = read_sum(c, &norm0, s)) != SAL_OK) return st;
     norm0 = std::sqrt(norm0);
     for (int k = 0; k < max_iter; ++k) {
-        SAL_HIP(launch_taubin_half(c->pos[0], c->pos[1], c->seg[ph], c->cols, c->list[ph], n, lam,
-                                   ph == 0, c->partials, c->sum, s));
+        SAL_HIP(launch_taubin_half(c->pos[0], c->pos[1], c->seg[ph], c->head[ph], c->cols,
+                                   c->list[ph], n, lam, ph == 0, c->partials, c->sum, s));
         SAL_HIP(hipMemcpyAsync(&step, c->sum, sizeof(double), hipMemcpyDeviceToHost, s));
-        SAL_HIP(launch_taubin_half(c->pos[1], c->pos[0], c->seg[ph], c->cols, c->list[ph], n, -mu,
-                                   ph == 0, c->partials, c->sum, s));
+        SAL_HIP(launch_taubin_half(c->pos[1], c->pos[0], c->seg[ph], c->head[ph], c->cols,
+                                   c->list[ph], n, -mu, ph == 0, c->partials, c->sum, s));
         SAL_HIP(hipStreamSynchronize(s));
         *iters = k + 1;
         *ratio = norm0 > 0.0 ? std::sqrt(step) / norm0 : 0.0;
