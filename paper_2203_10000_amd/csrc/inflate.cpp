@@ -86,6 +86,9 @@ sal_status sal_tet_mesh_inflate(sal_context *ctx, sal_tet_mesh *m, const sal_sur
         if ((st = b.get(&items, n_items)) != SAL_OK) return st;
         SAL_HIP(launch_fill_i32(count, 0, n_bins + 1, s));
         SAL_HIP(launch_bin_triangles(tri, n_tri, v.g, 1, count, start, items, s));
+        float *bin_tri = nullptr;
+        if ((st = b.get(&bin_tri, 9 * n_items)) != SAL_OK) return st;
+        SAL_HIP(launch_gather_binned(tri, items, n_items, bin_tri, s));
         SAL_HIP(hipEventRecord(ctx->ev[1], s));
         // move the interface nodes
         const int64_t n = c->n_list[0];
@@ -93,8 +96,8 @@ sal_status sal_tet_mesh_inflate(sal_context *ctx, sal_tet_mesh *m, const sal_sur
         if ((st = b.get(&partials, 2 * inflate_blocks(n))) != SAL_OK || (st = b.get(&sums, 2)) != SAL_OK)
             return st;
         SAL_HIP(launch_pack_pos(v.xyz, c->order, v.n_nodes, c->pos[0], c->pos[1], s));
-        SAL_HIP(launch_inflate(c->pos[0], c->pos[1], c->seg[0], c->cols, c->list[0], n, c->order, v.keys, tri,
-                               start, items, v.g, zeta, partials, sums, s));
+        SAL_HIP(launch_inflate(c->pos[0], c->pos[1], c->seg[0], c->cols, c->list[0], n, c->order, v.keys,
+                               bin_tri, start, v.g, zeta, partials, sums, s));
         SAL_HIP(hipEventRecord(ctx->ev[2], s));
         SAL_HIP(launch_unpack_pos(c->pos[1], c->order, v.n_nodes, v.xyz, s));
         double hs[2] = {0.0, 0.0};

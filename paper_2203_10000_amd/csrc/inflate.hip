@@ -104,6 +104,17 @@ __global__ void k_bin_triangles(const float *__restrict__ tri, int64_t n_tri, La
             }
 }
 
+// The triangles of each bin copied in bin order (9 floats per entry), so the
+// tests of a bin read their triangles at consecutive addresses instead of
+// through the item list (one dependent load less per test).
+__global__ void k_gather_binned(const float *__restrict__ tri, const int32_t *__restrict__ items,
+                                int64_t n_items, float *__restrict__ binned) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (entry, coordinate)
+    if (k >= 9 * n_items) return;
+    const int64_t r = k / 9;
+    binned[k] = tri[9 * (int64_t)items[r] + (k - 9 * r)];
+}
+
 // Segment p -> p + d against triangle tv (9 floats): t in [0, 1], or -1.
 __device__ __forceinline__ double crossing(const double p[3], const double d[3], const float *tv) {
 #pragma clang fp contract(off)
@@ -130,11 +141,14 @@ __device__ __forceinline__ double crossing(const double p[3], const double d[3],
 // triangles of the covered bins; the group keeps the entry with the
 // smallest (distance, neighbour key) and its first lane writes the moved
 // node into `out` (which holds every position on entry).
-__global__ __launch_bounds__(kSmoothThreads) void k_inflate(
+// Five wavefronts per SIMD (96 VGPRs, 12 bytes spilled) instead of the four
+// that 102 VGPRs allow: on c3 the call took 15.2 ms against 16.5 ms; six
+// (84 bytes spilled) measured the same as five.
+__global__ __launch_bounds__(kSmoothThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_inflate(
     const float4 *__restrict__ in, float4 *__restrict__ out, const uint64_t *__restrict__ seg,
     const uint32_t *__restrict__ cols, const int32_t *__restrict__ list, int64_t n,
-    const int32_t *__restrict__ order, const int64_t *__restrict__ keys, const float *__restrict__ tri,
-    const int64_t *__restrict__ bin_start, const int32_t *__restrict__ bin_items, LatticeGeom g,
+    const int32_t *__restrict__ order, const int64_t *__restrict__ keys,
+    const float *__restrict__ bin_tri, const int64_t *__restrict__ bin_start, LatticeGeom g,
     double zeta, double *__restrict__ partials) {
 #pragma clang fp contract(off)
     constexpr int G = kInflateGroup;
@@ -171,7 +185,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_inflate(
                     for (int x = b.lo[0]; x <= b.hi[0]; ++x) {
                         const int64_t k = bin_index(x, y, z, g);
                         for (int64_t r = bin_start[k], e = bin_start[k + 1]; r < e; ++r) {
-                            const double tt = crossing(p, d, tri + 9 * (int64_t)bin_items[r]);
+                            const double tt = crossing(p, d, bin_tri + 9 * r);
                             tests += 1.0;
                             if (tt >= 0.0 && tt < tmin) tmin = tt;
                         }
@@ -279,15 +293,21 @@ hipError_t exclusive_sum_bins(const int32_t *count, int64_t *start, int64_t n, v
                                    rocprim::plus<int64_t>(), s);
 }
 
+hipError_t launch_gather_binned(const float *tri, const int32_t *items, int64_t n_items, float *binned,
+                                hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_gather_binned<<<grid_of(9 * n_items), kSmoothThreads, 0, s>>>(tri, items, n_items, binned);
+    return hipGetLastError();
+}
+
 hipError_t launch_inflate(const float4 *in, float4 *out, const uint64_t *seg, const uint32_t *cols,
                           const int32_t *list, int64_t n, const int32_t *order, const int64_t *keys,
-                          const float *tri, const int64_t *bin_start, const int32_t *bin_items,
-                          const LatticeGeom &g, double zeta, double *partials, double *sums,
-                          hipStream_t s) {
+                          const float *bin_tri, const int64_t *bin_start, const LatticeGeom &g,
+                          double zeta, double *partials, double *sums, hipStream_t s) {
     const int64_t nb = inflate_blocks(n);
     if (nb > 0)
-        k_inflate<<<(unsigned)nb, kSmoothThreads, 0, s>>>(in, out, seg, cols, list, n, order, keys, tri,
-                                                          bin_start, bin_items, g, zeta, partials);
+        k_inflate<<<(unsigned)nb, kSmoothThreads, 0, s>>>(in, out, seg, cols, list, n, order, keys,
+                                                          bin_tri, bin_start, g, zeta, partials);
     k_sum_pairs<<<1, 1024, 0, s>>>(partials, nb, sums);
     return hipGetLastError();
 }

@@ -122,13 +122,16 @@ hipError_t launch_bin_triangles(const float *tri, int64_t n_tri, const LatticeGe
                                 int32_t *count, const int64_t *start, int32_t *items, hipStream_t s);
 hipError_t exclusive_sum_bins(const int32_t *count, int64_t *start, int64_t n, void *tmp, size_t *tmp_bytes,
                               hipStream_t s);
+// binned[9 r + c] = tri[9 items[r] + c]: the triangles of every bin, in bin order.
+hipError_t launch_gather_binned(const float *tri, const int32_t *items, int64_t n_items, float *binned,
+                                hipStream_t s);
 // Moves the listed (interface) nodes; out must hold every position on entry.
-// sums[0] = nodes moved, sums[1] = triangle tests.
+// sums[0] = nodes moved, sums[1] = triangle tests.  bin_tri: the binned
+// triangles (launch_gather_binned), bin k's entries at [bin_start[k], bin_start[k + 1]).
 hipError_t launch_inflate(const float4 *in, float4 *out, const uint64_t *seg, const uint32_t *cols,
                           const int32_t *list, int64_t n, const int32_t *order, const int64_t *keys,
-                          const float *tri, const int64_t *bin_start, const int32_t *bin_items,
-                          const LatticeGeom &g, double zeta, double *partials, double *sums,
-                          hipStream_t s);
+                          const float *bin_tri, const int64_t *bin_start, const LatticeGeom &g,
+                          double zeta, double *partials, double *sums, hipStream_t s);
 int64_t inflate_blocks(int64_t n);
 
 // Builds the edge graph on first use (smooth.cpp).
