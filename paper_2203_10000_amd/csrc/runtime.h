@@ -46,7 +46,8 @@ struct sal_surface_set {
     sal::Rec32 *rec32 = nullptr;
     sal::Rec64 *rec64 = nullptr;
     sal::SurfaceDev *surf = nullptr;        // n_surf entries, then the two tuner entries
-    sal::SurfaceDev *tune_surf = nullptr;   // surf + n_surf: [0] float32 trials, [1] FP64 trials
+    sal::SurfaceDev *tune_surf = nullptr;   // surf + n_surf: [0] float32 trials, [1] FP64 trials,
+                                            // [2] float32 screening trials
     int64_t *strip_off = nullptr;
     std::vector<sal::SurfaceDev> host_table;
     std::vector<int64_t> host_strip_off;   // record index of every strip head

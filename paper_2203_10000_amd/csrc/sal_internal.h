@@ -50,8 +50,11 @@ constexpr float kKnSmall = 5.0f;     // small-angle path needs D > 5 |n| r_Z + .
 constexpr int kMaxSurfaces = 64;     // per-point masks are 64-bit
 
 // Per-surface table in device memory.
-// Triangles per tuner trial launch: float32 form, FP64 form.
-constexpr int64_t kTuneTri[2] = {32768, 8192};
+// Triangles per tuner trial launch: float32 form, FP64 form, and the float32
+// screening launches (every shape once, before the closest two are timed on
+// the first prefix).
+constexpr int kTuneEntries = 3;
+constexpr int64_t kTuneTri[kTuneEntries] = {32768, 8192, 8192};
 
 struct SurfaceDev {
     int64_t rec_begin, rec_end;      // [begin, end) in both record streams

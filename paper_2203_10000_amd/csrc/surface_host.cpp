@@ -356,10 +356,10 @@ sal_status build_surface_records(const sal_surface_desc *desc, int32_t n, uint32
         sd.strip_end = (int64_t)strip_off.size();
     }
 
-    // Two extra table entries for the launch-shape tuner: the leading whole
+    // Extra table entries for the launch-shape tuner: the leading whole
     // strips of the record stream up to about kTuneTri[i] triangles, so that
     // a trial launch costs a bounded number of pairs on any mesh.
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kTuneEntries; ++i) {
         SurfaceDev t{};
         int64_t s = 0, tris = 0;
         while (s < (int64_t)strip_off.size() && tris < kTuneTri[i]) tris += strip_tris[(size_t)s++];
