@@ -60,6 +60,10 @@ constexpr int kSmoothThreads = 256;
 #endif
 constexpr int kTaubinGroup = SAL_TAUBIN_GROUP;     // lanes per node in a half step (power of 2)
 constexpr int kTaubinUnroll = SAL_TAUBIN_UNROLL;   // entries per lane loaded together
+#ifndef SAL_TAUBIN_WINDOW
+#define SAL_TAUBIN_WINDOW 256
+#endif
+constexpr int kTaubinWindow = SAL_TAUBIN_WINDOW;   // positions a half-step block may stage in LDS
 
 // Edge graph construction.
 // *bad_labels counts tetrahedra with a label outside [-1, 254].
