@@ -113,8 +113,16 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
             return st;
 
         const bool replay = opt.use_graph && ctx->batch_graph && ctx->batch_graph_key == key;
+        // an eager call on the batch whose work list is already on the device
+        // skips the host-side build and upload
+        const bool reuse = !replay && !opt.use_graph && ctx->batch_items_key == key;
         BatchArgs a{};
-        if (!replay) {
+        if (reuse) a.n_items = ctx->batch_n_items;
+        if (!replay && !reuse) {
+            // the item and instance buffers are about to be rewritten: a graph
+            // captured for another batch reads them, so it is stale from here
+            ctx->batch_graph_key = 0;
+            ctx->batch_items_key = 0;
             // ---- work list: (instance, block, surface, strip range), largest first
             const int64_t resident_waves = (int64_t)ctx->n_cu * 32;
             int64_t cap = total_pairs / (8 * resident_waves);
@@ -211,6 +219,8 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
             SAL_HIP(hipMemcpy(ctx->batch_insts, hin.data(), hin.size() * sizeof(BatchInst),
                               hipMemcpyHostToDevice));
             a.n_items = (int64_t)sorted.size();
+            ctx->batch_items_key = key;
+            ctx->batch_n_items = a.n_items;
         }
         a.items = (const BatchItem *)ctx->batch_items;
         a.insts = (const BatchInst *)ctx->batch_insts;

@@ -36,6 +36,8 @@ struct sal_context {
     hipGraphExec_t batch_graph = nullptr;
     uint64_t batch_graph_key = 0;
     int64_t batch_graph_points = 0;
+    uint64_t batch_items_key = 0;   // batch whose work list the item buffers hold (0: none)
+    int64_t batch_n_items = 0;
 };
 
 struct sal_surface_set {

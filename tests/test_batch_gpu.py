@@ -101,6 +101,30 @@ def test_batch_graph_replays(ctx, precision):
         assert np.array_equal(lab.cpu().numpy(), oracle.label(q, surfs))
 
 
+def test_batch_work_list_reuse_and_graph_invalidation(ctx):
+    """Eager calls on the same batch reuse the device work list; an eager call
+    on another batch rewrites it, so a graph captured earlier must be captured
+    again (not replayed on the other batch's work list)."""
+    ia, ib = small_instances(3, seed=30), small_instances(4, seed=40)
+    da, db = build(ctx, ia), build(ctx, ib)
+
+    def check(insts, dev):
+        torch.cuda.synchronize()
+        for (surfs, pts), (_, _, lab) in zip(insts, dev):
+            assert np.array_equal(lab.cpu().numpy(), oracle.label(pts, surfs))
+
+    def clear(dev):
+        for _, _, lab in dev:
+            lab.fill_(-7)
+
+    for step, (insts, dev, graph) in enumerate([(ia, da, True), (ib, db, False), (ia, da, True),
+                                                (ia, da, False), (ia, da, False), (ib, db, False),
+                                                (ia, da, False), (ia, da, True)]):
+        clear(dev)
+        sal.label_batch(ctx, dev, use_graph=graph)
+        check(insts, dev)
+
+
 def test_batch_fp64_form(ctx):
     """The persistent FP64 kernel: labels equal the per-point FP64 form's and
     the oracle's, points exactly on a triangle count as enclosed, and the
