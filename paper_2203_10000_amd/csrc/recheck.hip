@@ -185,7 +185,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_rc_pairs(RecheckArgs a) {
                 const float lim = fmaf(q7, cr, fmaf(kap, mm, fabsf(nn)));
                 // Per-lane choice (not wave-uniform as in the pair loop): a pair's
                 // terms must not depend on which pairs share its wavefront.
-                if (dd > lim) {
+                if (__builtin_expect(dd > lim, 1)) {   // the common case as the fall-through path
                     const float u = nn * __builtin_amdgcn_rcpf(dd);
                     const float s2 = u * u;
                     accf = fmaf(u, fmaf(fmaf(mixed::kA2, s2, mixed::kA1), s2, mixed::kA0), accf);

@@ -75,7 +75,7 @@ __device__ __forceinline__ double strip_sum(const Rec32 *__restrict__ rec32,
         const float mm = rr01 * cr;
         const float dd = fmaf(e12, ar, fmaf(e02, br, fmaf(e01, cr, mm)));
         const float lim = fmaf(q[7], cr, fmaf(kap, mm, fabsf(nn)));
-        if (dd > lim) {
+        if (__builtin_expect(dd > lim, 1)) {   // the common case as the fall-through path
             const float u = nn * __builtin_amdgcn_rcpf(dd);
             const float s = u * u;
             accf = fmaf(u, fmaf(fmaf(kA2, s, kA1), s, kA0), accf);
