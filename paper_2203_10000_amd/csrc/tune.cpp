@@ -147,6 +147,10 @@ sal_status tune_launch(sal_context *ctx, const sal_surface_set *set, int64_t n, 
     // ~300 ms.
     int n_final = nc;
     if (!fp64 && nc > 2) {
+        // one untimed launch first, so that the first screened shape does not
+        // also pay for the device warming up
+        float warm = 0.0f;
+        if ((ts = time_shape(cand[0], 2, 1, &warm)) != SAL_OK) return ts;
         for (int k = 0; k < nc; ++k)
             if ((ts = time_shape(cand[k], 2, 1, &cand[k].ms)) != SAL_OK) return ts;
         for (int k = 0; k < 2; ++k)   // the two fastest to the front, in order
