@@ -85,26 +85,31 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
 
         const bool fp64 = opt.precision == SAL_PREC_FP64;
 
-        // cache key of this batch (graph replay)
-        uint64_t key = 0x51ed270b2717ull;
+        // cache key of this batch (work-list reuse, graph replay): the fields
+        // themselves, compared in full, and their hash as a quick first test
+        std::vector<uint64_t> fields;
+        fields.reserve((size_t)n_inst * 6 + 5);
         for (int i = 0; i < n_inst; ++i) {
-            key = mix(key, inst[i].surfaces->uid);
-            key = mix(key, (uint64_t)inst[i].n_points);
-            key = mix(key, (uint64_t)(uintptr_t)inst[i].x);
-            key = mix(key, (uint64_t)(uintptr_t)inst[i].y);
-            key = mix(key, (uint64_t)(uintptr_t)inst[i].z);
-            key = mix(key, (uint64_t)(uintptr_t)inst[i].labels);
+            fields.push_back(inst[i].surfaces->uid);
+            fields.push_back((uint64_t)inst[i].n_points);
+            fields.push_back((uint64_t)(uintptr_t)inst[i].x);
+            fields.push_back((uint64_t)(uintptr_t)inst[i].y);
+            fields.push_back((uint64_t)(uintptr_t)inst[i].z);
+            fields.push_back((uint64_t)(uintptr_t)inst[i].labels);
         }
-        double kd = opt.kappa;
+        const double kd = opt.kappa;
         uint64_t kb;
         std::memcpy(&kb, &kd, 8);
-        key = mix(key, kb);
+        fields.push_back(kb);
         std::memcpy(&kb, &opt.threshold, 8);
-        key = mix(key, kb);
+        fields.push_back(kb);
         std::memcpy(&kb, &opt.recheck_band, 8);
-        key = mix(key, kb);
-        key = mix(key, (uint64_t)n_inst);
-        key = mix(key, fp64 ? 2u : 1u);
+        fields.push_back(kb);
+        fields.push_back((uint64_t)n_inst);
+        fields.push_back(fp64 ? 2u : 1u);
+        uint64_t key = 0x51ed270b2717ull;
+        for (const uint64_t f : fields) key = mix(key, f);
+        if (key == 0) key = 1;   // 0 marks "no batch"
 
         st = ensure_flag_capacity(ctx, total);
         if (st != SAL_OK) return st;
@@ -112,10 +117,12 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
                              (int64_t)n_inst * kNumCounters, s, ctx)) != SAL_OK)
             return st;
 
-        const bool replay = opt.use_graph && ctx->batch_graph && ctx->batch_graph_key == key;
+        const bool replay = opt.use_graph && ctx->batch_graph && ctx->batch_graph_key == key &&
+                            ctx->batch_graph_fields == fields;
         // an eager call on the batch whose work list is already on the device
         // skips the host-side build and upload
-        const bool reuse = !replay && !opt.use_graph && ctx->batch_items_key == key;
+        const bool reuse = !replay && !opt.use_graph && ctx->batch_items_key == key &&
+                           ctx->batch_items_fields == fields;
         BatchArgs a{};
         if (reuse) a.n_items = ctx->batch_n_items;
         if (!replay && !reuse) {
@@ -220,6 +227,7 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
                               hipMemcpyHostToDevice));
             a.n_items = (int64_t)sorted.size();
             ctx->batch_items_key = key;
+            ctx->batch_items_fields = fields;
             ctx->batch_n_items = a.n_items;
         }
         a.items = (const BatchItem *)ctx->batch_items;
@@ -270,6 +278,7 @@ extern "C" sal_status sal_label_batch(sal_context *ctx, const sal_instance *inst
                 (void)hipGraphDestroy(g);
                 if (ee != hipSuccess) return hip_error(ee, "hipGraphInstantiate");
                 ctx->batch_graph_key = key;
+                ctx->batch_graph_fields = fields;
                 ctx->batch_graph_points = total;
             }
             SAL_HIP(hipGraphLaunch(ctx->batch_graph, s));

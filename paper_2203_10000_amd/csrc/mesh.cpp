@@ -82,6 +82,7 @@ struct sal_tet_mesh {
     sal::RoundState *rs = nullptr;
     hipGraphExec_t round_graph = nullptr;
     uint64_t round_key = 0;
+    std::vector<uint64_t> round_fields;   // the fields hashed into round_key
     // four-node rule: level-0 node grid masks, per-leaf vertex masks of
     // levels >= 1, masks of the labeled midpoints
     int rule = -1;   // element rule fixed by the first labeling
@@ -425,14 +426,6 @@ uint64_t mix(uint64_t h, uint64_t v) {
     return h;
 }
 
-uint64_t mixp(uint64_t h, const void *p) { return mix(h, (uint64_t)(uintptr_t)p); }
-
-uint64_t mixd(uint64_t h, double d) {
-    uint64_t u;
-    std::memcpy(&u, &d, sizeof u);
-    return mix(h, u);
-}
-
 int64_t *rs_n(sal::RoundState *rs) {
     return (int64_t *)((char *)rs + offsetof(sal::RoundState, n));
 }
@@ -533,38 +526,51 @@ sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set
             return st;
     }
 
-    uint64_t key = mix(0x5a1d5a1dull, set->uid);
-    key = mixp(key, ctx);
-    key = mixp(key, ctx->flag_list);
-    key = mixp(key, ctx->rc_pairs);
-    key = mixp(key, ctx->rc_out);
-    key = mixp(key, ctx->rc_res);
-    key = mixp(key, ctx->rc_seg);
-    key = mix(key, (uint64_t)ctx->flag_cap);
-    key = mix(key, (uint64_t)ctx->rc_pair_cap);
-    key = mixp(key, ctx->counters);
-    key = mix(key, (uint64_t)opt.precision);
-    key = mixd(key, opt.threshold);
-    key = mixd(key, opt.recheck_band);
-    key = mixd(key, opt.kappa);
-    key = mix(key, (uint64_t)opt.points_per_lane);
-    key = mix(key, (uint64_t)opt.block_waves);
-    key = mix(key, (uint64_t)opt.cull_bounds);
+    // Everything the captured round reads or is shaped by: compared in full
+    // (a hash of it is the quick first test) before a replay.
+    std::vector<uint64_t> f;
+    auto add = [&](uint64_t v) { f.push_back(v); };
+    auto addp = [&](const void *p) { f.push_back((uint64_t)(uintptr_t)p); };
+    auto addd = [&](double d) {
+        uint64_t u;
+        std::memcpy(&u, &d, sizeof u);
+        f.push_back(u);
+    };
+    add(set->uid);
+    addp(ctx);
+    addp(ctx->flag_list);
+    addp(ctx->rc_pairs);
+    addp(ctx->rc_out);
+    addp(ctx->rc_res);
+    addp(ctx->rc_seg);
+    add((uint64_t)ctx->flag_cap);
+    add((uint64_t)ctx->rc_pair_cap);
+    addp(ctx->counters);
+    add((uint64_t)opt.precision);
+    addd(opt.threshold);
+    addd(opt.recheck_band);
+    addd(opt.kappa);
+    add((uint64_t)opt.points_per_lane);
+    add((uint64_t)opt.block_waves);
+    add((uint64_t)opt.cull_bounds);
     for (int l = 0; l <= kMaxLevels; ++l) {
-        key = mixp(key, m->key[l]);
-        key = mixp(key, m->label[l]);
-        key = mixp(key, m->child[l]);
-        key = mixp(key, m->flag[l]);
-        key = mix(key, (uint64_t)m->cap[l]);
+        addp(m->key[l]);
+        addp(m->label[l]);
+        addp(m->child[l]);
+        addp(m->flag[l]);
+        add((uint64_t)m->cap[l]);
     }
-    for (auto *c : m->cen) key = mixp(key, c);
-    key = mixp(key, m->lab_scratch);
-    key = mixp(key, m->list);
-    key = mixp(key, m->blocks);
-    key = mixp(key, m->totals);
-    key = mixp(key, m->rs);
-    key = mix(key, (uint64_t)kid_cap);
-    const bool capture = !m->round_graph || m->round_key != key;
+    for (auto *c : m->cen) addp(c);
+    addp(m->lab_scratch);
+    addp(m->list);
+    addp(m->blocks);
+    addp(m->totals);
+    addp(m->rs);
+    add((uint64_t)kid_cap);
+    uint64_t key = 0x5a1d5a1dull;
+    for (const uint64_t v : f) key = mix(key, v);
+    if (key == 0) key = 1;   // 0 marks "no graph"
+    const bool capture = !m->round_graph || m->round_key != key || m->round_fields != f;
     if (capture) {
         if (m->round_graph) {
             SAL_HIP(hipGraphExecDestroy(m->round_graph));
@@ -585,6 +591,7 @@ sal_status graph_rounds(sal_context *ctx, sal_tet_mesh *m, const sal_surface_set
         (void)hipGraphDestroy(g);
         if (ee != hipSuccess) return hip_error(ee, "hipGraphInstantiate");
         m->round_key = key;
+        m->round_fields = f;
     }
 
     RoundState h{};

@@ -35,8 +35,10 @@ struct sal_context {
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t batch_graph = nullptr;
     uint64_t batch_graph_key = 0;
+    std::vector<uint64_t> batch_graph_fields;   // the fields hashed into batch_graph_key
     int64_t batch_graph_points = 0;
     uint64_t batch_items_key = 0;   // batch whose work list the item buffers hold (0: none)
+    std::vector<uint64_t> batch_items_fields;   // the fields hashed into batch_items_key
     int64_t batch_n_items = 0;
 };
 
